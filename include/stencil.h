@@ -1,0 +1,193 @@
+/*
+ * stencil.h -- C ABI of the MI355X (gfx950) stencil-sweep library
+ * (libstencil.so).
+ *
+ * What it computes.  A stencil sweep replaces every cell of a d-dimensional
+ * grid, once per time step, by a weighted sum of itself and a fixed set of
+ * neighbours taken from the previous step (paper: Sec. 2.1 and its Alg. 1
+ * "Heat-2D Stencil"; the explicit heat step of Eq. 3 is the special case of a
+ * radius-1 star with centre weight 1 - 2*d*mu and neighbour weights mu).  The
+ * library runs T such steps, blocked in space (tiles held on chip) and in
+ * time (several steps fused per pass over memory; Sec. 4 "Locality
+ * Enhancer"), and returns u_T = S^T(u_0).  Reordering and fusing the updates
+ * changes only rounding, not the result (Sec. 1, the two key observations).
+ *
+ * Conventions shared by every entry point.
+ *   Layout   dense C order, shape (nz, ny, nx) in 3D, (ny, nx) in 2D, (nx) in
+ *            1D; x is unit-stride, as j is in Alg. 1.  No padding.
+ *   Offsets  npoints x ndim int32, slowest axis first; the centre (all zero)
+ *            must be among them.  |offset| <= 4 on every axis; npoints <= 125.
+ *   Boundary ST_BC_ZERO: an index outside the grid reads 0 (a zero-Dirichlet
+ *            ghost layer around the grid, so every cell evolves);
+ *            ST_BC_PERIODIC: indices wrap modulo the extent.
+ *   Steps    exactly `steps` updates; steps == 0 is a no-op returning ST_OK.
+ *   Coeffs   host FP64, one weight per point in the caller's point order; the
+ *            library rounds each to the compute precision once (FP64 for
+ *            ST_F64 storage, FP32 for ST_F32 and ST_BF16 storage).
+ *   Memory   grid and work buffers are device pointers owned by the caller;
+ *            the library never frees them.  Plans, their device tables and
+ *            any plan-owned workspace belong to the library.
+ *   Streams  `stream` is a hipStream_t passed as void* (NULL = the null
+ *            stream).  Runs are asynchronous and stream-ordered; the result is
+ *            in `grid` once the stream reaches it.  Nothing in a run
+ *            synchronises the host.
+ *   Errors   every call returns st_status and never throws or aborts.
+ *            Argument problems are found on the host before any launch.  A
+ *            HIP failure returns ST_ERR_HIP; stencil_last_error() then names
+ *            the call site and the HIP error string (thread-local).
+ *   Threads  distinct plans may be used from distinct threads; one plan must
+ *            not be run concurrently from two threads.
+ */
+#ifndef PAPER_2303_08365_AMD_STENCIL_H
+#define PAPER_2303_08365_AMD_STENCIL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ST_OK = 0,
+    ST_ERR_ARG = -1,          /* NULL pointer, bad size, bad enum value         */
+    ST_ERR_UNSUPPORTED = -2,  /* ndim not in 1..3, radius > 4, npoints > 125,  */
+                              /* a flag the pattern cannot take               */
+    ST_ERR_MISMATCH = -3,     /* shape/boundary/count differs from the plan     */
+    ST_ERR_NOMEM = -4,        /* host or device allocation failed               */
+    ST_ERR_HIP = -5,          /* a HIP runtime call failed (see last_error)     */
+    ST_ERR_CAPTURE = -6       /* an allocating call made during stream capture  */
+} st_status;
+
+typedef enum { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 } st_dtype;   /* storage type */
+typedef enum { ST_BC_ZERO = 0, ST_BC_PERIODIC = 1 } st_boundary;
+
+/* Plan flags. */
+#define ST_PLAN_AUTOTUNE 0x1u  /* time candidate tilings on the device now;    */
+                               /* allocates and synchronises (not capturable)  */
+#define ST_PLAN_NAIVE 0x2u     /* force the one-step-per-launch kernel         */
+#define ST_PLAN_VARCOEF 0x4u   /* variable-coefficient heat operator (3D,      */
+                               /* radius-1 star, ST_BC_ZERO only)              */
+
+typedef struct {
+    int32_t ndim;             /* 1..3                                          */
+    int32_t npoints;          /* 1..125                                        */
+    const int32_t* offsets;   /* host, npoints*ndim, copied by the plan call  */
+} st_pattern;
+
+typedef struct st_plan_s* st_plan;
+
+/* Kernel families a plan can select. */
+#define ST_KERNEL_NAIVE 0      /* one step per launch, any pattern             */
+#define ST_KERNEL_STREAM2D 1   /* 2D star/box, rows streamed through registers */
+#define ST_KERNEL_STREAM3D 2   /* 3D star, planes streamed, LDS row exchange   */
+#define ST_KERNEL_VARCOEF3D 3  /* 3D variable-coefficient heat                 */
+
+typedef struct {
+    int32_t kernel;           /* ST_KERNEL_*                                    */
+    int32_t tb;               /* time steps fused per pass                      */
+    int32_t radius;           /* max |offset|                                   */
+    int32_t shape_class;      /* 0 general, 1 star, 2 box                       */
+    int32_t tile_x, tile_y, tile_z;  /* output cells per work-group tile        */
+    int32_t block;            /* threads per work-group                         */
+    int64_t workgroups;       /* work-groups per pass launch (single grid)      */
+    int64_t lds_bytes;        /* LDS per work-group                             */
+    int32_t variant;          /* index of the tiling candidate                  */
+    int32_t ncandidates;      /* tiling candidates valid for this plan          */
+} st_plan_info;
+
+/*
+ * stencil_plan -- choose kernel, tile, fused depth and launch geometry for
+ * one grid shape (paper Sec. 5.2: the scheduler is fixed from a profile of the
+ * problem; Tab. 1 lists the blocking sizes per benchmark).
+ *   out      receives the plan; *out is NULL on failure.
+ *   pattern  point list (copied).  Points are evaluated in a canonical order
+ *            (centre, then lexicographic by offset) by every kernel, so all
+ *            tilings and depths of one plan give bit-identical results.
+ *   shape    pattern->ndim extents, each >= 1.
+ *   storage  ST_F64 computes in FP64; ST_F32 and ST_BF16 compute in FP32
+ *            (ST_BF16 rounds every step's result to bfloat16, ties to even).
+ *   flags    ST_PLAN_* bits.  With ST_PLAN_AUTOTUNE the call allocates two
+ *            scratch grids, times every candidate on the current device and
+ *            keeps the fastest; without it a fixed heuristic is used.
+ * Errors: ST_ERR_ARG, ST_ERR_UNSUPPORTED, ST_ERR_NOMEM, ST_ERR_HIP (autotune).
+ */
+st_status stencil_plan(st_plan* out, const st_pattern* pattern, const int64_t* shape,
+                       st_dtype storage, st_boundary bc, uint32_t flags);
+
+/* Release a plan and everything it owns (NULL is accepted). */
+st_status stencil_plan_destroy(st_plan plan);
+
+/* Describe the plan's current choice. */
+st_status stencil_plan_info(st_plan plan, st_plan_info* info);
+
+/*
+ * stencil_plan_candidate -- describe tiling candidate `index` of the plan
+ * (0 <= index < info->ncandidates of stencil_plan_info).
+ */
+st_status stencil_plan_candidate(st_plan plan, int32_t index, st_plan_info* info);
+
+/*
+ * stencil_plan_select -- force a kernel family, fused depth and tiling
+ * candidate (used by the autotuner and by tests that compare candidates).
+ * kernel = -1 keeps the family; tb <= 0 keeps the depth; variant < 0 keeps
+ * the candidate.  Returns ST_ERR_UNSUPPORTED when the combination cannot run
+ * this plan.
+ */
+st_status stencil_plan_select(st_plan plan, int32_t kernel, int32_t tb, int32_t variant);
+
+/*
+ * stencil_run -- run `steps` steps on one grid (Alg. 1 with T = steps).
+ *   grid    device, in: u_0, out: u_T; plan->shape cells of the storage type.
+ *   work    device buffer of the same size, clobbered; NULL makes the plan
+ *           allocate and keep one on first use (that first call allocates
+ *           and is then not capturable into a HIP graph).
+ *   coeffs  host FP64 weights, one per pattern point, caller's order.
+ *   shape   must equal the plan's shape (ST_ERR_MISMATCH otherwise).
+ *   bc      must equal the plan's boundary (ST_ERR_MISMATCH otherwise).
+ * The steps are grouped into passes of up to tb fused steps; passes
+ * alternate between grid and work and the pass list is arranged so that the
+ * last pass writes `grid`.  run(a) followed by run(b) equals run(a + b) bit
+ * for bit.  Unstable coefficients are not an error.
+ */
+st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs,
+                      const int64_t* shape, int64_t steps, st_boundary bc, void* stream);
+
+/*
+ * stencil_batch_plan -- plan a batch of n independent grids that share the
+ * pattern, storage type and boundary but differ in shape and coefficients
+ * (an ensemble).  Each pass over all grids is ONE launch: work-groups take
+ * (grid, tile) items from a device descriptor table (paper Sec. 5.2: the
+ * work is split so that no worker becomes the slowest).  Supported patterns:
+ * 2D star or box.  shapes: host, n * ndim extents.
+ * Errors: ST_ERR_ARG, ST_ERR_UNSUPPORTED, ST_ERR_NOMEM, ST_ERR_HIP.
+ */
+st_status stencil_batch_plan(st_plan* out, const st_pattern* pattern, int32_t n,
+                             const int64_t* shapes, st_dtype storage, st_boundary bc,
+                             uint32_t flags);
+
+/*
+ * stencil_batch_run -- run grid g for steps[g] steps, for every g, in
+ * ceil(max steps / tb) launches on `stream`.
+ *   grids, works  host arrays of n device pointers (work buffers as in
+ *                 stencil_run, required here).
+ *   coeffs        host FP64, n * npoints, row g holds grid g's weights.
+ *   steps         host, n step counts (each >= 0).
+ * Results land in grids[g].  The plan uploads a descriptor table per call
+ * through a plan-owned pinned buffer (waiting, if needed, for the previous
+ * call's upload to finish reading it).
+ * Errors: ST_ERR_ARG, ST_ERR_MISMATCH (n differs from the plan), ST_ERR_HIP.
+ */
+st_status stencil_batch_run(st_plan plan, int32_t n, void* const* grids, void* const* works,
+                            const double* coeffs, const int64_t* steps, void* stream);
+
+/* Thread-local text of the last failure ("" if none). */
+const char* stencil_last_error(void);
+
+/* Library version string. */
+const char* stencil_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_2303_08365_AMD_STENCIL_H */

@@ -1,0 +1,269 @@
+"""MI355X (gfx950) stencil sweep -- Python binding of libstencil.so.
+
+Argument marshalling only: every step of the sweep runs in the library's HIP
+kernels.  PyTorch supplies device memory (``tensor.data_ptr()``) and the
+stream (``torch.cuda.current_stream().cuda_stream``).  If the built library
+is missing, every entry point raises -- there is no CPU fallback.
+
+Names follow include/stencil.h: ``Plan`` wraps ``stencil_plan`` /
+``stencil_run``; ``BatchPlan`` wraps ``stencil_batch_plan`` /
+``stencil_batch_run``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence
+
+__all__ = [
+    "StencilError", "Plan", "BatchPlan", "run", "library", "library_path", "build",
+    "F64", "F32", "BF16", "BC_ZERO", "BC_PERIODIC", "PLAN_AUTOTUNE", "PLAN_NAIVE",
+    "PLAN_VARCOEF", "KERNEL_NAIVE", "KERNEL_STREAM2D", "KERNEL_STREAM3D", "KERNEL_VARCOEF3D",
+    "STATUS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libstencil.so")
+
+F64, F32, BF16 = 0, 1, 2
+BC_ZERO, BC_PERIODIC = 0, 1
+PLAN_AUTOTUNE, PLAN_NAIVE, PLAN_VARCOEF = 0x1, 0x2, 0x4
+KERNEL_NAIVE, KERNEL_STREAM2D, KERNEL_STREAM3D, KERNEL_VARCOEF3D = 0, 1, 2, 3
+STATUS = {0: "ST_OK", -1: "ST_ERR_ARG", -2: "ST_ERR_UNSUPPORTED", -3: "ST_ERR_MISMATCH",
+          -4: "ST_ERR_NOMEM", -5: "ST_ERR_HIP", -6: "ST_ERR_CAPTURE"}
+_DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
+_BCS = {"zero": BC_ZERO, "periodic": BC_PERIODIC, BC_ZERO: BC_ZERO, BC_PERIODIC: BC_PERIODIC}
+
+
+class StencilError(RuntimeError):
+    """A libstencil call returned a status other than ST_OK."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("tb", ctypes.c_int32), ("radius", ctypes.c_int32),
+                ("shape_class", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("workgroups", ctypes.c_int64), ("lds_bytes", ctypes.c_int64),
+                ("variant", ctypes.c_int32), ("ncandidates", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class _Pattern(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("npoints", ctypes.c_int32),
+                ("offsets", ctypes.POINTER(ctypes.c_int32))]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def build(force: bool = False) -> str:
+    """Compile the HIP library in-tree (see buildlib.py)."""
+    from . import buildlib
+    return buildlib.build(force=force)
+
+
+def library():
+    """The loaded libstencil.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"libstencil.so is not built at {_LIB_PATH}; run build() first")
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        p_i64 = ctypes.POINTER(ctypes.c_int64)
+        p_dbl = ctypes.POINTER(ctypes.c_double)
+        sig = {
+            "stencil_plan": [ctypes.POINTER(P), ctypes.POINTER(_Pattern), p_i64, i32, i32, u32],
+            "stencil_plan_destroy": [P],
+            "stencil_plan_info": [P, ctypes.POINTER(PlanInfo)],
+            "stencil_plan_candidate": [P, i32, ctypes.POINTER(PlanInfo)],
+            "stencil_plan_select": [P, i32, i32, i32],
+            "stencil_run": [P, P, P, p_dbl, p_i64, i64, i32, P],
+            "stencil_batch_plan": [ctypes.POINTER(P), ctypes.POINTER(_Pattern), i32, p_i64, i32, i32, u32],
+            "stencil_batch_run": [P, i32, ctypes.POINTER(P), ctypes.POINTER(P), p_dbl, p_i64, P],
+        }
+        for name, args in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        lib.stencil_last_error.argtypes = []
+        lib.stencil_last_error.restype = ctypes.c_char_p
+        lib.stencil_version.argtypes = []
+        lib.stencil_version.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = library().stencil_last_error().decode(errors="replace")
+        raise StencilError(status, msg)
+
+
+def _pattern(offsets: Sequence[Sequence[int]]):
+    offs = [tuple(int(v) for v in o) for o in offsets]
+    if not offs:
+        raise ValueError("empty point list")
+    ndim = len(offs[0])
+    flat = (ctypes.c_int32 * (len(offs) * ndim))(*[v for o in offs for v in o])
+    pat = _Pattern(ndim, len(offs), ctypes.cast(flat, ctypes.POINTER(ctypes.c_int32)))
+    return pat, flat
+
+
+def _doubles(vals: Iterable[float]):
+    v = [float(x) for x in vals]
+    return (ctypes.c_double * len(v))(*v)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _tensor_dtype(t) -> int:
+    import torch
+    m = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported tensor dtype {t.dtype}")
+    return m[t.dtype]
+
+
+class Plan:
+    """A plan for one grid shape (``stencil_plan``)."""
+
+    def __init__(self, offsets, shape, dtype="f64", bc="zero", autotune=False, naive=False):
+        lib = library()
+        self.offsets = [tuple(int(v) for v in o) for o in offsets]
+        self.shape = tuple(int(s) for s in shape)
+        self.dtype = _DTYPES[dtype]
+        self.bc = _BCS[bc]
+        flags = (PLAN_AUTOTUNE if autotune else 0) | (PLAN_NAIVE if naive else 0)
+        pat, self._flat = _pattern(self.offsets)
+        shp = (ctypes.c_int64 * len(self.shape))(*self.shape)
+        h = ctypes.c_void_p()
+        _check(lib.stencil_plan(ctypes.byref(h), ctypes.byref(pat), shp, self.dtype, self.bc, flags))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().stencil_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = PlanInfo()
+        _check(library().stencil_plan_info(self._h, ctypes.byref(i)))
+        return i.as_dict()
+
+    def candidates(self) -> List[dict]:
+        n = self.info()["ncandidates"]
+        out = []
+        for k in range(n):
+            i = PlanInfo()
+            _check(library().stencil_plan_candidate(self._h, k, ctypes.byref(i)))
+            out.append(i.as_dict())
+        return out
+
+    def select(self, kernel: int = -1, tb: int = 0, variant: int = -1):
+        _check(library().stencil_plan_select(self._h, int(kernel), int(tb), int(variant)))
+        return self
+
+    def run(self, grid, coeffs, steps: int, work=None, stream=None):
+        """Run `steps` steps in place on the device tensor `grid`."""
+        if tuple(grid.shape) != self.shape:
+            raise ValueError(f"grid shape {tuple(grid.shape)} != plan shape {self.shape}")
+        if not grid.is_contiguous() or _tensor_dtype(grid) != self.dtype:
+            raise ValueError("grid must be a contiguous tensor of the plan's dtype")
+        if work is not None and (work.numel() != grid.numel() or work.dtype != grid.dtype):
+            raise ValueError("work must match grid in size and dtype")
+        w = _doubles(coeffs)
+        if len(w) != len(self.offsets):
+            raise ValueError("one coefficient per point")
+        shp = (ctypes.c_int64 * len(self.shape))(*self.shape)
+        _check(library().stencil_run(self._h, grid.data_ptr(),
+                                     work.data_ptr() if work is not None else None, w, shp,
+                                     int(steps), self.bc, _stream_handle(stream)))
+        return grid
+
+
+class BatchPlan:
+    """A plan for a batch of 2D grids (``stencil_batch_plan``)."""
+
+    def __init__(self, offsets, shapes, dtype="f32", bc="zero"):
+        lib = library()
+        self.offsets = [tuple(int(v) for v in o) for o in offsets]
+        self.shapes = [tuple(int(s) for s in sh) for sh in shapes]
+        self.dtype = _DTYPES[dtype]
+        self.bc = _BCS[bc]
+        pat, self._flat = _pattern(self.offsets)
+        flat = [s for sh in self.shapes for s in sh]
+        shp = (ctypes.c_int64 * len(flat))(*flat)
+        h = ctypes.c_void_p()
+        _check(lib.stencil_batch_plan(ctypes.byref(h), ctypes.byref(pat), len(self.shapes), shp,
+                                      self.dtype, self.bc, 0))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().stencil_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = PlanInfo()
+        _check(library().stencil_plan_info(self._h, ctypes.byref(i)))
+        return i.as_dict()
+
+    def select(self, kernel: int = -1, tb: int = 0, variant: int = -1):
+        _check(library().stencil_plan_select(self._h, int(kernel), int(tb), int(variant)))
+        return self
+
+    def run(self, grids, works, coeffs, steps, stream=None):
+        n = len(self.shapes)
+        if len(grids) != n or len(works) != n or len(coeffs) != n or len(steps) != n:
+            raise ValueError("one grid, work buffer, coefficient row and step count per batch entry")
+        for g, w, sh in zip(grids, works, self.shapes):
+            if tuple(g.shape) != sh or not g.is_contiguous() or _tensor_dtype(g) != self.dtype:
+                raise ValueError("grid shape/dtype/contiguity differs from the plan")
+            if w.numel() != g.numel() or w.dtype != g.dtype:
+                raise ValueError("work must match its grid")
+        gp = (ctypes.c_void_p * n)(*[g.data_ptr() for g in grids])
+        wp = (ctypes.c_void_p * n)(*[w.data_ptr() for w in works])
+        cf = _doubles([c for row in coeffs for c in row])
+        st = (ctypes.c_int64 * n)(*[int(s) for s in steps])
+        _check(library().stencil_batch_run(self._h, n, gp, wp, cf, st, _stream_handle(stream)))
+        return grids
+
+
+def run(grid, coeffs, offsets, steps: int, bc="zero", plan: Optional[Plan] = None, work=None,
+        stream=None):
+    """One-shot sweep: plan (unless given) and run in place on `grid`."""
+    if plan is None:
+        plan = Plan(offsets, tuple(grid.shape), _tensor_dtype(grid), bc)
+    return plan.run(grid, coeffs, steps, work=work, stream=stream)

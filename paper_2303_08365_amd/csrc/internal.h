@@ -1,0 +1,84 @@
+// internal.h -- argument blocks and launchers shared by the host side
+// (stencil_abi.cpp) and the kernel translation units.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace st {
+
+constexpr int kMaxPoints = 125;
+constexpr int kMaxRadius = 4;
+
+enum Dtype : int32_t { kF64 = 0, kF32 = 1, kBF16 = 2 };
+enum Bc : int32_t { kZero = 0, kPeriodic = 1 };
+enum Cls : int32_t { kGeneral = 0, kStar = 1, kBox = 2 };
+
+// ----------------------------------------------------------------------------
+// one step per launch, any pattern (the reference form of every other kernel)
+// ----------------------------------------------------------------------------
+struct NaiveArgs {
+    const void* src;
+    void* dst;
+    int64_t n[3];              // nz, ny, nx (leading 1s for lower ndim)
+    int32_t npoints;
+    int32_t bc;
+    int32_t off[kMaxPoints][3];  // canonical order, centre first
+    double w[kMaxPoints];        // weights already rounded to compute precision
+};
+hipError_t launch_naive(int dtype, const NaiveArgs& a, hipStream_t s);
+
+// ----------------------------------------------------------------------------
+// 2D: rows streamed through registers, T_b fused steps per pass
+// ----------------------------------------------------------------------------
+// A wave owns an x strip of 64*VX columns (its register tile) and walks the
+// rows of one y chunk.  Level l of the pipeline holds 2R+1 rows of step l.
+struct Stream2DGrid {
+    const void* src;
+    void* dst;
+    int64_t ny, nx;
+    int32_t tiles_x;     // strips across x
+    int32_t chunks_y;    // y chunks
+    int32_t chunk_y;     // output rows per chunk
+    int32_t out_w;       // output columns per strip = 64*VX - 2*hxa
+    int32_t hxa;         // redundant halo columns each side (multiple of VX)
+    int32_t vec_ok;      // rows and base are aligned for whole-vector access
+    int32_t tb;          // fused steps this pass (<= template depth)
+    int64_t tile_begin;  // first work item of this grid in the batch
+    double w[32];        // canonical-order weights
+};
+struct Stream2DArgs {
+    const Stream2DGrid* grids;  // device table (batch) or nullptr
+    Stream2DGrid one;           // used when grids == nullptr
+    int32_t ngrids;
+    int64_t items;              // total (grid, strip, chunk) work items
+};
+// Instantiation key for the 2D family.
+struct Stream2DKey {
+    int32_t dtype, bc, cls, radius, tbmax, vx;
+};
+hipError_t launch_stream2d(const Stream2DKey& k, const Stream2DArgs& a, hipStream_t s);
+bool stream2d_has(const Stream2DKey& k);
+
+// ----------------------------------------------------------------------------
+// 3D star: planes streamed along z, K rows per lane, LDS edge-row exchange
+// ----------------------------------------------------------------------------
+struct Stream3DArgs {
+    const void* src;
+    void* dst;
+    int64_t nz, ny, nx;
+    int32_t tiles_x, tiles_y, chunks_z;
+    int32_t out_w, out_h, chunk_z;
+    int32_t hxa, hya;    // redundant halo columns/rows inside the register tile
+    int32_t vec_ok;
+    int32_t tb;
+    double w[32];        // canonical-order weights (6R+1 used)
+};
+struct Stream3DKey {
+    int32_t dtype, bc, radius, tbmax, vx, k, nw;
+};
+hipError_t launch_stream3d(const Stream3DKey& k, const Stream3DArgs& a, hipStream_t s);
+bool stream3d_has(const Stream3DKey& k);
+int stream3d_lds_bytes(const Stream3DKey& k);
+
+}  // namespace st

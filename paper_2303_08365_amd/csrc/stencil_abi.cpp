@@ -1,0 +1,858 @@
+// stencil_abi.cpp -- host side of libstencil.so: argument checks, plans,
+// candidate tilings, pass scheduling and the extern "C" entry points
+// declared in include/stencil.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/stencil.h"
+#include "internal.h"
+
+using namespace st;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+namespace {
+
+thread_local std::string g_last_error;
+
+st_status fail(st_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+st_status hip_fail(hipError_t e, const char* site) {
+    return fail(ST_ERR_HIP, "%s: %s (%d)", site, hipGetErrorString(e), static_cast<int>(e));
+}
+
+#define ST_HIP(call, site)                       \
+    do {                                         \
+        hipError_t e_ = (call);                  \
+        if (e_ != hipSuccess) return hip_fail(e_, site); \
+    } while (0)
+
+// A device is needed for anything that launches.  Asked once per process.
+st_status need_device() {
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    static int count = 0;
+    std::call_once(once, [] { err = hipGetDeviceCount(&count); });
+    if (err != hipSuccess) return hip_fail(err, "hipGetDeviceCount");
+    if (count < 1) return fail(ST_ERR_HIP, "hipGetDeviceCount: no HIP device");
+    return ST_OK;
+}
+
+// LDS bytes one work-group may use on the current device.
+int device_lds_limit() {
+    static std::once_flag once;
+    static int limit = 65536;
+    std::call_once(once, [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            limit = v;
+    });
+    return limit;
+}
+
+bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st == hipStreamCaptureStatusActive;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+int elem_bytes(int dtype) { return dtype == kF64 ? 8 : (dtype == kF32 ? 4 : 2); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+namespace {
+
+// One tiling candidate of a plan.
+struct Candidate {
+    int32_t kernel = ST_KERNEL_NAIVE;
+    int32_t tb = 1;
+    Stream2DKey k2{};
+    Stream3DKey k3{};
+    int32_t chunk = 0;  // y chunk (2D) or z chunk (3D); 0 = automatic
+};
+
+struct BatchGrid {
+    int64_t ny, nx;
+};
+
+}  // namespace
+
+struct st_plan_s {
+    int32_t ndim = 0;
+    int64_t shape[3] = {1, 1, 1};  // caller's extents (ndim used)
+    int64_t n[3] = {1, 1, 1};      // nz, ny, nx
+    int32_t dtype = kF64;
+    int32_t bc = kZero;
+    uint32_t flags = 0;
+    int32_t npoints = 0;
+    int32_t off[kMaxPoints][3] = {};  // canonical order, padded to 3D
+    int32_t perm[kMaxPoints] = {};    // canonical index -> caller's index
+    int32_t radius = 0;
+    int32_t cls = kGeneral;
+    std::vector<Candidate> cands;
+    int32_t sel = 0;
+    void* owned_work = nullptr;
+    size_t owned_bytes = 0;
+    // batch
+    bool batch = false;
+    std::vector<BatchGrid> grids;
+    void* table_dev = nullptr;
+    void* table_host = nullptr;   // pinned
+    size_t table_cap = 0;         // bytes
+    hipEvent_t table_done = nullptr;
+    bool table_pending = false;
+};
+
+namespace {
+
+int64_t plan_cells(const st_plan_s* p) { return p->n[0] * p->n[1] * p->n[2]; }
+
+// Classify the (canonical) point set.
+void classify(st_plan_s* p) {
+    int r = 0;
+    for (int i = 0; i < p->npoints; ++i)
+        for (int d = 0; d < 3; ++d) r = std::max(r, std::abs(p->off[i][d]));
+    p->radius = r;
+    p->cls = kGeneral;
+    if (r == 0) return;
+    const int first = 3 - p->ndim;  // first real axis
+    auto has = [&](int dz, int dy, int dx) {
+        for (int i = 0; i < p->npoints; ++i)
+            if (p->off[i][0] == dz && p->off[i][1] == dy && p->off[i][2] == dx) return true;
+        return false;
+    };
+    // star: centre + every axis point up to r, nothing else
+    int star_n = 1 + 2 * p->ndim * r;
+    if (p->npoints == star_n) {
+        bool ok = true;
+        for (int a = first; a < 3 && ok; ++a)
+            for (int d = 1; d <= r && ok; ++d)
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    int o[3] = {0, 0, 0};
+                    o[a] = sg * d;
+                    if (!has(o[0], o[1], o[2])) { ok = false; break; }
+                }
+        if (ok) { p->cls = kStar; return; }
+    }
+    int box_n = 1;
+    for (int a = 0; a < p->ndim; ++a) box_n *= 2 * r + 1;
+    if (p->npoints == box_n) p->cls = kBox;  // points are distinct and within radius r
+}
+
+// Geometry of one 2D pass for a grid.
+struct Geo2 {
+    int32_t hxa, out_w, tiles_x, chunk_y, chunks_y;
+    int64_t items;
+};
+
+bool geo2(const Candidate& c, int64_t ny, int64_t nx, int tb, Geo2& g) {
+    const int vx = c.k2.vx, R = c.k2.radius;
+    g.hxa = static_cast<int32_t>(round_up(static_cast<int64_t>(R) * (tb - 1), vx));
+    g.out_w = 64 * vx - 2 * g.hxa;
+    if (g.out_w <= 0) return false;
+    g.tiles_x = static_cast<int32_t>(ceil_div(nx, g.out_w));
+    int64_t chunk = c.chunk;
+    if (chunk <= 0) {
+        // about 2048 waves per pass: two per SIMD on 256 CUs
+        const int64_t want = std::max<int64_t>(1, 2048 / g.tiles_x);
+        chunk = std::max<int64_t>(std::max<int64_t>(16, 4 * R * tb), ceil_div(ny, want));
+    }
+    chunk = std::min<int64_t>(chunk, ny);
+    g.chunk_y = static_cast<int32_t>(chunk);
+    g.chunks_y = static_cast<int32_t>(ceil_div(ny, chunk));
+    g.items = static_cast<int64_t>(g.tiles_x) * g.chunks_y;
+    return true;
+}
+
+struct Geo3 {
+    int32_t hxa, hya, out_w, out_h, tiles_x, tiles_y, chunk_z, chunks_z;
+};
+
+bool geo3(const Candidate& c, const int64_t n[3], int tb, Geo3& g) {
+    const int vx = c.k3.vx, R = c.k3.radius, H = c.k3.k * c.k3.nw;
+    g.hxa = static_cast<int32_t>(round_up(static_cast<int64_t>(R) * (tb - 1), vx));
+    g.hya = R * (tb - 1);
+    g.out_w = 64 * vx - 2 * g.hxa;
+    g.out_h = H - 2 * g.hya;
+    if (g.out_w <= 0 || g.out_h <= 0) return false;
+    g.tiles_x = static_cast<int32_t>(ceil_div(n[2], g.out_w));
+    g.tiles_y = static_cast<int32_t>(ceil_div(n[1], g.out_h));
+    int64_t chunk = c.chunk;
+    const int64_t per_plane = static_cast<int64_t>(g.tiles_x) * g.tiles_y;
+    if (chunk <= 0) {
+        const int64_t want = std::max<int64_t>(1, ceil_div(1024, per_plane));
+        chunk = std::max<int64_t>(std::max<int64_t>(8, 4 * R * tb), ceil_div(n[0], want));
+    }
+    chunk = std::min<int64_t>(chunk, n[0]);
+    g.chunk_z = static_cast<int32_t>(chunk);
+    g.chunks_z = static_cast<int32_t>(ceil_div(n[0], chunk));
+    return per_plane * g.chunks_z < (int64_t(1) << 31);
+}
+
+// Default fused depth and lane width per family.
+int default_vx2(int dtype) { return dtype == kF64 ? 2 : (dtype == kF32 ? 4 : 8); }
+
+void build_candidates(st_plan_s* p) {
+    p->cands.clear();
+    Candidate naive;
+    naive.kernel = ST_KERNEL_NAIVE;
+    naive.tb = 1;
+    const bool force_naive = (p->flags & ST_PLAN_NAIVE) != 0;
+    std::vector<Candidate> fast;
+    if (!force_naive && p->ndim == 2 && p->radius == 1 && (p->cls == kStar || p->cls == kBox)) {
+        const int vx = default_vx2(p->dtype);
+        const int tbs[] = {1, 2, 4, 8};
+        for (int tb : tbs) {
+            for (int tbmax : {1, 4, 8}) {
+                if (tbmax < tb) continue;
+                Candidate c;
+                c.kernel = ST_KERNEL_STREAM2D;
+                c.tb = tb;
+                c.k2 = Stream2DKey{p->dtype, p->bc, p->cls, p->radius, tbmax, vx};
+                Geo2 g;
+                if (stream2d_has(c.k2) && geo2(c, p->n[1], p->n[2], tb, g)) {
+                    fast.push_back(c);
+                    break;  // smallest instance that holds tb
+                }
+            }
+        }
+        // heuristic default first: deeper fusion for narrower storage
+        const int want = p->dtype == kF64 ? 4 : 8;
+        std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
+            return (a.tb == want) > (b.tb == want);
+        });
+    }
+    if (!force_naive && p->ndim == 3 && p->cls == kStar && (p->radius == 1 || p->radius == 4)) {
+        struct V { int vx, k, nw; };
+        std::vector<V> vs;
+        if (p->radius == 1) {
+            if (p->dtype == kF64) vs = {{2, 4, 4}, {2, 2, 8}};
+            else if (p->dtype == kF32) vs = {{4, 4, 4}, {4, 2, 8}};
+            else vs = {{4, 4, 4}};
+        } else {
+            if (p->dtype == kF64) vs = {{4, 1, 8}};
+            else if (p->dtype == kF32) vs = {{4, 2, 8}, {4, 1, 16}};
+            else vs = {{4, 2, 8}};
+        }
+        for (int tb = 1; tb <= 4; ++tb) {
+            for (const V& v : vs) {
+                for (int tbmax : {1, 2, 4}) {
+                    if (tbmax < tb) continue;
+                    Candidate c;
+                    c.kernel = ST_KERNEL_STREAM3D;
+                    c.tb = tb;
+                    c.k3 = Stream3DKey{p->dtype, p->bc, p->radius, tbmax, v.vx, v.k, v.nw};
+                    Geo3 g;
+                    if (stream3d_has(c.k3) && geo3(c, p->n, tb, g)) {
+                        fast.push_back(c);
+                        break;
+                    }
+                }
+            }
+        }
+        const int want = 1;
+        std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
+            return (a.tb == want) > (b.tb == want);
+        });
+    }
+    p->cands = fast;
+    p->cands.push_back(naive);
+    p->sel = 0;
+    // environment overrides (testing and tuning): STENCIL_TB, STENCIL_VARIANT
+    if (const char* v = std::getenv("STENCIL_VARIANT")) {
+        const int i = std::atoi(v);
+        if (i >= 0 && i < static_cast<int>(p->cands.size())) p->sel = i;
+    } else if (const char* t = std::getenv("STENCIL_TB")) {
+        const int tb = std::atoi(t);
+        for (size_t i = 0; i < p->cands.size(); ++i)
+            if (p->cands[i].tb == tb) { p->sel = static_cast<int>(i); break; }
+    }
+}
+
+st_status check_pattern(const st_pattern* pat) {
+    if (!pat) return fail(ST_ERR_ARG, "pattern is NULL");
+    if (pat->ndim < 1 || pat->ndim > 3) return fail(ST_ERR_UNSUPPORTED, "ndim %d not in 1..3", pat->ndim);
+    if (pat->npoints < 1 || pat->npoints > kMaxPoints)
+        return fail(pat->npoints < 1 ? ST_ERR_ARG : ST_ERR_UNSUPPORTED, "npoints %d not in 1..%d",
+                    pat->npoints, kMaxPoints);
+    if (!pat->offsets) return fail(ST_ERR_ARG, "pattern offsets are NULL");
+    bool centre = false;
+    for (int i = 0; i < pat->npoints; ++i) {
+        bool zero = true;
+        for (int d = 0; d < pat->ndim; ++d) {
+            const int o = pat->offsets[i * pat->ndim + d];
+            if (o < -kMaxRadius || o > kMaxRadius)
+                return fail(ST_ERR_UNSUPPORTED, "offset %d of point %d exceeds radius %d", o, i, kMaxRadius);
+            zero = zero && o == 0;
+        }
+        centre = centre || zero;
+        for (int j = 0; j < i; ++j) {
+            bool same = true;
+            for (int d = 0; d < pat->ndim; ++d)
+                same = same && pat->offsets[i * pat->ndim + d] == pat->offsets[j * pat->ndim + d];
+            if (same) return fail(ST_ERR_ARG, "points %d and %d coincide", j, i);
+        }
+    }
+    if (!centre) return fail(ST_ERR_ARG, "the centre point (all offsets 0) is missing");
+    return ST_OK;
+}
+
+st_status fill_plan(st_plan_s* p, const st_pattern* pat, st_dtype storage, st_boundary bc, uint32_t flags) {
+    if (storage != ST_F64 && storage != ST_F32 && storage != ST_BF16)
+        return fail(ST_ERR_ARG, "storage dtype %d unknown", static_cast<int>(storage));
+    if (bc != ST_BC_ZERO && bc != ST_BC_PERIODIC) return fail(ST_ERR_ARG, "boundary %d unknown", static_cast<int>(bc));
+    if (flags & ~(ST_PLAN_AUTOTUNE | ST_PLAN_NAIVE | ST_PLAN_VARCOEF))
+        return fail(ST_ERR_ARG, "unknown flag bits 0x%x", flags);
+    if (flags & ST_PLAN_VARCOEF) return fail(ST_ERR_UNSUPPORTED, "variable-coefficient plans are not available");
+    p->ndim = pat->ndim;
+    p->dtype = storage;
+    p->bc = bc;
+    p->flags = flags;
+    p->npoints = pat->npoints;
+    // canonical order: centre first, then lexicographic by padded offset
+    std::vector<std::array<int, 4>> pts;
+    for (int i = 0; i < pat->npoints; ++i) {
+        std::array<int, 4> o = {0, 0, 0, i};
+        for (int d = 0; d < pat->ndim; ++d) o[3 - pat->ndim + d] = pat->offsets[i * pat->ndim + d];
+        pts.push_back(o);
+    }
+    std::sort(pts.begin(), pts.end(), [](const std::array<int, 4>& a, const std::array<int, 4>& b) {
+        const bool ca = a[0] == 0 && a[1] == 0 && a[2] == 0, cb = b[0] == 0 && b[1] == 0 && b[2] == 0;
+        if (ca != cb) return ca;
+        return std::lexicographical_compare(a.begin(), a.begin() + 3, b.begin(), b.begin() + 3);
+    });
+    for (int i = 0; i < p->npoints; ++i) {
+        for (int d = 0; d < 3; ++d) p->off[i][d] = pts[i][d];
+        p->perm[i] = pts[i][3];
+    }
+    classify(p);
+    return ST_OK;
+}
+
+// Weights in canonical order, rounded once to the compute precision.
+void canonical_weights(const st_plan_s* p, const double* coeffs, double* out) {
+    for (int i = 0; i < p->npoints; ++i) {
+        const double w = coeffs[p->perm[i]];
+        out[i] = (p->dtype == kF64) ? w : static_cast<double>(static_cast<float>(w));
+    }
+}
+
+bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15u) == 0; }
+
+// Fused depths of the passes of one run: all tb except the remainder, and
+// arranged so that their count is even (the last pass then writes the
+// caller's grid).  `copy` is set when that is impossible (every pass is a
+// single step and the count is odd).
+std::vector<int> pass_list(int64_t steps, int tb, bool& copy) {
+    std::vector<int> v;
+    copy = false;
+    if (steps <= 0) return v;
+    for (int64_t s = 0; s + tb <= steps; s += tb) v.push_back(tb);
+    if (steps % tb) v.push_back(static_cast<int>(steps % tb));
+    if (v.size() % 2 == 1) {
+        // split the last pass of depth >= 2 into two
+        for (int i = static_cast<int>(v.size()) - 1; i >= 0; --i) {
+            if (v[i] >= 2) {
+                const int a = v[i] / 2, b = v[i] - a;
+                v[i] = a;
+                v.insert(v.begin() + i + 1, b);
+                return v;
+            }
+        }
+        copy = true;
+    }
+    return v;
+}
+
+st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, void* dst,
+                      const double* wcan, int tb, bool vec_ok, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (c.kernel == ST_KERNEL_NAIVE) {
+        NaiveArgs a;
+        a.src = src;
+        a.dst = dst;
+        for (int d = 0; d < 3; ++d) a.n[d] = p->n[d];
+        a.npoints = p->npoints;
+        a.bc = p->bc;
+        for (int i = 0; i < p->npoints; ++i) {
+            for (int d = 0; d < 3; ++d) a.off[i][d] = p->off[i][d];
+            a.w[i] = wcan[i];
+        }
+        for (int t = 0; t < tb && e == hipSuccess; ++t) {
+            // tb > 1 never reaches here: the naive family runs single steps
+            e = launch_naive(p->dtype, a, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "naive launch");
+        return ST_OK;
+    }
+    if (c.kernel == ST_KERNEL_STREAM2D) {
+        Geo2 g;
+        if (!geo2(c, p->n[1], p->n[2], tb, g)) return fail(ST_ERR_UNSUPPORTED, "2D tiling infeasible");
+        Stream2DArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.grids = nullptr;
+        a.ngrids = 1;
+        a.items = g.items;
+        Stream2DGrid& G = a.one;
+        G.src = src;
+        G.dst = dst;
+        G.ny = p->n[1];
+        G.nx = p->n[2];
+        G.tiles_x = g.tiles_x;
+        G.chunks_y = g.chunks_y;
+        G.chunk_y = g.chunk_y;
+        G.out_w = g.out_w;
+        G.hxa = g.hxa;
+        G.vec_ok = vec_ok ? 1 : 0;
+        G.tb = tb;
+        G.tile_begin = 0;
+        for (int i = 0; i < p->npoints; ++i) G.w[i] = wcan[i];
+        e = launch_stream2d(c.k2, a, s);
+        if (e != hipSuccess) return hip_fail(e, "stream2d launch");
+        return ST_OK;
+    }
+    if (c.kernel == ST_KERNEL_STREAM3D) {
+        Geo3 g;
+        if (!geo3(c, p->n, tb, g)) return fail(ST_ERR_UNSUPPORTED, "3D tiling infeasible");
+        const int lds = stream3d_lds_bytes(c.k3);
+        if (lds > device_lds_limit())
+            return fail(ST_ERR_UNSUPPORTED, "tiling needs %d bytes of LDS, the device allows %d", lds,
+                        device_lds_limit());
+        Stream3DArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.src = src;
+        a.dst = dst;
+        a.nz = p->n[0];
+        a.ny = p->n[1];
+        a.nx = p->n[2];
+        a.tiles_x = g.tiles_x;
+        a.tiles_y = g.tiles_y;
+        a.chunks_z = g.chunks_z;
+        a.out_w = g.out_w;
+        a.out_h = g.out_h;
+        a.chunk_z = g.chunk_z;
+        a.hxa = g.hxa;
+        a.hya = g.hya;
+        a.vec_ok = vec_ok ? 1 : 0;
+        a.tb = tb;
+        for (int i = 0; i < p->npoints; ++i) a.w[i] = wcan[i];
+        e = launch_stream3d(c.k3, a, s);
+        if (e != hipSuccess) return hip_fail(e, "stream3d launch");
+        return ST_OK;
+    }
+    return fail(ST_ERR_UNSUPPORTED, "kernel family %d unknown", c.kernel);
+}
+
+// Run `steps` steps with candidate c: grid -> work -> grid ...
+st_status run_steps(st_plan_s* p, const Candidate& c, void* grid, void* work, const double* wcan,
+                    int64_t steps, hipStream_t s) {
+    const int tb = (c.kernel == ST_KERNEL_NAIVE) ? 1 : c.tb;
+    bool copy = false;
+    const std::vector<int> passes = pass_list(steps, tb, copy);
+    const size_t bytes = static_cast<size_t>(plan_cells(p)) * elem_bytes(p->dtype);
+    const int vx = c.kernel == ST_KERNEL_STREAM2D ? c.k2.vx : (c.kernel == ST_KERNEL_STREAM3D ? c.k3.vx : 1);
+    const bool vec_ok = (p->n[2] % vx == 0) && aligned16(grid) && aligned16(work);
+    void* src = grid;
+    void* dst = work;
+    for (int t : passes) {
+        st_status r = launch_pass(p, c, src, dst, wcan, t, vec_ok, s);
+        if (r != ST_OK) return r;
+        std::swap(src, dst);
+    }
+    if (copy) ST_HIP(hipMemcpyAsync(grid, work, bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(work->grid)");
+    return ST_OK;
+}
+
+void describe(const st_plan_s* p, const Candidate& c, int index, st_plan_info* info) {
+    std::memset(info, 0, sizeof(*info));
+    info->kernel = c.kernel;
+    info->tb = c.kernel == ST_KERNEL_NAIVE ? 1 : c.tb;
+    info->radius = p->radius;
+    info->shape_class = p->cls;
+    info->variant = index;
+    info->ncandidates = static_cast<int32_t>(p->cands.size());
+    if (c.kernel == ST_KERNEL_NAIVE) {
+        info->tile_x = info->tile_y = info->tile_z = 1;
+        info->block = 256;
+        info->workgroups = ceil_div(plan_cells(p), 256);
+    } else if (c.kernel == ST_KERNEL_STREAM2D) {
+        Geo2 g;
+        geo2(c, p->n[1], p->n[2], c.tb, g);
+        info->tile_x = g.out_w;
+        info->tile_y = g.chunk_y;
+        info->tile_z = 1;
+        info->block = 256;
+        info->workgroups = ceil_div(g.items, 4);
+    } else if (c.kernel == ST_KERNEL_STREAM3D) {
+        Geo3 g;
+        geo3(c, p->n, c.tb, g);
+        info->tile_x = g.out_w;
+        info->tile_y = g.out_h;
+        info->tile_z = g.chunk_z;
+        info->block = 64 * c.k3.nw;
+        info->workgroups = static_cast<int64_t>(g.tiles_x) * g.tiles_y * g.chunks_z;
+        info->lds_bytes = stream3d_lds_bytes(c.k3);
+    }
+}
+
+st_status autotune(st_plan_s* p) {
+    if (st_status r = need_device(); r != ST_OK) return r;
+    if (p->cands.size() <= 1) return ST_OK;
+    const size_t bytes = static_cast<size_t>(plan_cells(p)) * elem_bytes(p->dtype);
+    void *a = nullptr, *b = nullptr;
+    ST_HIP(hipMalloc(&a, bytes), "hipMalloc(autotune)");
+    if (hipMalloc(&b, bytes) != hipSuccess) {
+        hipFree(a);
+        return fail(ST_ERR_NOMEM, "hipMalloc(autotune) failed");
+    }
+    hipMemset(a, 0, bytes);
+    double w[kMaxPoints];
+    for (int i = 0; i < p->npoints; ++i) w[i] = (i == 0) ? 1.0 - 0.1 * (p->npoints - 1) / p->npoints : 0.1 / p->npoints;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    double best = 1e300;
+    int best_i = p->sel;
+    for (size_t i = 0; i < p->cands.size(); ++i) {
+        const Candidate& c = p->cands[i];
+        const int64_t steps = std::max<int64_t>(2, 2 * c.tb);
+        if (run_steps(p, c, a, b, w, steps, nullptr) != ST_OK) continue;  // warm-up
+        hipEventRecord(e0, nullptr);
+        st_status r = ST_OK;
+        for (int rep = 0; rep < 3 && r == ST_OK; ++rep) r = run_steps(p, c, a, b, w, steps, nullptr);
+        hipEventRecord(e1, nullptr);
+        hipEventSynchronize(e1);
+        if (r != ST_OK) continue;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        const double per_step = ms / (3.0 * steps);
+        if (per_step < best) { best = per_step; best_i = static_cast<int>(i); }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(a);
+    hipFree(b);
+    p->sel = best_i;
+    g_last_error.clear();
+    return ST_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// extern "C"
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* stencil_last_error(void) { return g_last_error.c_str(); }
+
+const char* stencil_version(void) { return "paper_2303_08365_amd stencil 0.1 (gfx950)"; }
+
+st_status stencil_plan(st_plan* out, const st_pattern* pattern, const int64_t* shape, st_dtype storage,
+                       st_boundary bc, uint32_t flags) {
+    if (!out) return fail(ST_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (st_status r = check_pattern(pattern); r != ST_OK) return r;
+    if (!shape) return fail(ST_ERR_ARG, "shape is NULL");
+    for (int d = 0; d < pattern->ndim; ++d)
+        if (shape[d] < 1) return fail(ST_ERR_ARG, "shape[%d] = %lld < 1", d, static_cast<long long>(shape[d]));
+    st_plan_s* p = new (std::nothrow) st_plan_s();
+    if (!p) return fail(ST_ERR_NOMEM, "plan allocation failed");
+    if (st_status r = fill_plan(p, pattern, storage, bc, flags); r != ST_OK) {
+        delete p;
+        return r;
+    }
+    for (int d = 0; d < p->ndim; ++d) {
+        p->shape[d] = shape[d];
+        p->n[3 - p->ndim + d] = shape[d];
+    }
+    build_candidates(p);
+    if (flags & ST_PLAN_AUTOTUNE) {
+        if (st_status r = autotune(p); r != ST_OK) {
+            delete p;
+            return r;
+        }
+    }
+    *out = p;
+    return ST_OK;
+}
+
+st_status stencil_plan_destroy(st_plan plan) {
+    if (!plan) return ST_OK;
+    if (plan->owned_work) hipFree(plan->owned_work);
+    if (plan->table_dev) hipFree(plan->table_dev);
+    if (plan->table_host) hipHostFree(plan->table_host);
+    if (plan->table_done) hipEventDestroy(plan->table_done);
+    delete plan;
+    return ST_OK;
+}
+
+st_status stencil_plan_info(st_plan plan, st_plan_info* info) {
+    if (!plan || !info) return fail(ST_ERR_ARG, "plan or info is NULL");
+    describe(plan, plan->cands[plan->sel], plan->sel, info);
+    return ST_OK;
+}
+
+st_status stencil_plan_candidate(st_plan plan, int32_t index, st_plan_info* info) {
+    if (!plan || !info) return fail(ST_ERR_ARG, "plan or info is NULL");
+    if (index < 0 || index >= static_cast<int32_t>(plan->cands.size()))
+        return fail(ST_ERR_ARG, "candidate %d not in 0..%zu", index, plan->cands.size() - 1);
+    describe(plan, plan->cands[index], index, info);
+    return ST_OK;
+}
+
+st_status stencil_plan_select(st_plan plan, int32_t kernel, int32_t tb, int32_t variant) {
+    if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
+    const int n = static_cast<int>(plan->cands.size());
+    if (variant >= 0) {
+        if (variant >= n) return fail(ST_ERR_UNSUPPORTED, "candidate %d not in 0..%d", variant, n - 1);
+        const Candidate& c = plan->cands[variant];
+        if ((kernel >= 0 && c.kernel != kernel) || (tb > 0 && c.tb != tb))
+            return fail(ST_ERR_UNSUPPORTED, "candidate %d is kernel %d depth %d", variant, c.kernel, c.tb);
+        plan->sel = variant;
+        return ST_OK;
+    }
+    for (int i = 0; i < n; ++i) {
+        const Candidate& c = plan->cands[i];
+        if ((kernel < 0 || c.kernel == kernel) && (tb <= 0 || c.tb == tb)) {
+            plan->sel = i;
+            return ST_OK;
+        }
+    }
+    return fail(ST_ERR_UNSUPPORTED, "no candidate with kernel %d and depth %d", kernel, tb);
+}
+
+st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs, const int64_t* shape,
+                      int64_t steps, st_boundary bc, void* stream) {
+    if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
+    if (plan->batch) return fail(ST_ERR_MISMATCH, "batch plan passed to stencil_run");
+    if (!shape) return fail(ST_ERR_ARG, "shape is NULL");
+    for (int d = 0; d < plan->ndim; ++d)
+        if (shape[d] != plan->shape[d])
+            return fail(ST_ERR_MISMATCH, "shape[%d] = %lld, plan has %lld", d, static_cast<long long>(shape[d]),
+                        static_cast<long long>(plan->shape[d]));
+    if (bc != plan->bc) return fail(ST_ERR_MISMATCH, "boundary %d, plan has %d", static_cast<int>(bc), plan->bc);
+    if (steps < 0) return fail(ST_ERR_ARG, "steps = %lld < 0", static_cast<long long>(steps));
+    if (steps == 0) return ST_OK;
+    if (!grid) return fail(ST_ERR_ARG, "grid is NULL");
+    if (!coeffs) return fail(ST_ERR_ARG, "coeffs is NULL");
+    for (int i = 0; i < plan->npoints; ++i)
+        if (!std::isfinite(coeffs[i])) return fail(ST_ERR_ARG, "coefficient %d is not finite", i);
+    if (st_status r = need_device(); r != ST_OK) return r;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t bytes = static_cast<size_t>(plan_cells(plan)) * elem_bytes(plan->dtype);
+    if (!work) {
+        if (!plan->owned_work) {
+            if (stream_capturing(s)) return fail(ST_ERR_CAPTURE, "work == NULL needs an allocation during capture");
+            if (hipMalloc(&plan->owned_work, bytes) != hipSuccess) {
+                plan->owned_work = nullptr;
+                return fail(ST_ERR_NOMEM, "hipMalloc(%zu) for the plan's work buffer failed", bytes);
+            }
+            plan->owned_bytes = bytes;
+        }
+        work = plan->owned_work;
+    }
+    if (work == grid) return fail(ST_ERR_ARG, "work aliases grid");
+    double wcan[kMaxPoints];
+    canonical_weights(plan, coeffs, wcan);
+    return run_steps(plan, plan->cands[plan->sel], grid, work, wcan, steps, s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batch
+// ---------------------------------------------------------------------------
+extern "C" st_status stencil_batch_plan(st_plan* out, const st_pattern* pattern, int32_t n,
+                                        const int64_t* shapes, st_dtype storage, st_boundary bc,
+                                        uint32_t flags) {
+    if (!out) return fail(ST_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (st_status r = check_pattern(pattern); r != ST_OK) return r;
+    if (n < 1) return fail(ST_ERR_ARG, "batch of %d grids", n);
+    if (!shapes) return fail(ST_ERR_ARG, "shapes is NULL");
+    if (pattern->ndim != 2) return fail(ST_ERR_UNSUPPORTED, "batched plans take 2D patterns");
+    for (int64_t i = 0; i < static_cast<int64_t>(n) * 2; ++i)
+        if (shapes[i] < 1) return fail(ST_ERR_ARG, "shapes[%lld] < 1", static_cast<long long>(i));
+    st_plan_s* p = new (std::nothrow) st_plan_s();
+    if (!p) return fail(ST_ERR_NOMEM, "plan allocation failed");
+    if (st_status r = fill_plan(p, pattern, storage, bc, flags & ~ST_PLAN_AUTOTUNE); r != ST_OK) {
+        delete p;
+        return r;
+    }
+    if (p->radius != 1 || (p->cls != kStar && p->cls != kBox)) {
+        delete p;
+        return fail(ST_ERR_UNSUPPORTED, "batched plans take radius-1 star or box patterns");
+    }
+    p->batch = true;
+    p->flags = flags;
+    int64_t maxy = 1, maxx = 1;
+    for (int g = 0; g < n; ++g) {
+        p->grids.push_back(BatchGrid{shapes[2 * g], shapes[2 * g + 1]});
+        maxy = std::max(maxy, shapes[2 * g]);
+        maxx = std::max(maxx, shapes[2 * g + 1]);
+    }
+    p->shape[0] = maxy;
+    p->shape[1] = maxx;
+    p->n[1] = maxy;
+    p->n[2] = maxx;
+    build_candidates(p);
+    // batch runs need a fused family; drop the naive fallback when one exists
+    if (p->cands.size() > 1) p->cands.pop_back();
+    *out = p;
+    return ST_OK;
+}
+
+extern "C" st_status stencil_batch_run(st_plan plan, int32_t n, void* const* grids, void* const* works,
+                                       const double* coeffs, const int64_t* steps, void* stream) {
+    if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
+    if (!plan->batch) return fail(ST_ERR_MISMATCH, "single-grid plan passed to stencil_batch_run");
+    if (n != static_cast<int32_t>(plan->grids.size()))
+        return fail(ST_ERR_MISMATCH, "batch of %d grids, plan has %zu", n, plan->grids.size());
+    if (!grids || !works || !coeffs || !steps) return fail(ST_ERR_ARG, "NULL batch array");
+    int64_t maxsteps = 0;
+    for (int g = 0; g < n; ++g) {
+        if (steps[g] < 0) return fail(ST_ERR_ARG, "steps[%d] < 0", g);
+        if (steps[g] > 0 && (!grids[g] || !works[g])) return fail(ST_ERR_ARG, "grid %d has a NULL buffer", g);
+        if (steps[g] > 0 && grids[g] == works[g]) return fail(ST_ERR_ARG, "grid %d: work aliases grid", g);
+        maxsteps = std::max(maxsteps, steps[g]);
+        for (int i = 0; i < plan->npoints; ++i)
+            if (!std::isfinite(coeffs[static_cast<int64_t>(g) * plan->npoints + i]))
+                return fail(ST_ERR_ARG, "coefficient %d of grid %d is not finite", i, g);
+    }
+    if (maxsteps == 0) return ST_OK;
+    if (st_status r = need_device(); r != ST_OK) return r;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Candidate& c = plan->cands[plan->sel];
+    if (c.kernel == ST_KERNEL_NAIVE) {
+        // pattern without a fused family: grid by grid
+        st_plan_s one = *plan;
+        one.batch = false;
+        one.owned_work = nullptr;
+        one.table_dev = one.table_host = nullptr;
+        one.table_done = nullptr;
+        for (int g = 0; g < n; ++g) {
+            if (steps[g] == 0) continue;
+            one.n[1] = plan->grids[g].ny;
+            one.n[2] = plan->grids[g].nx;
+            double w[kMaxPoints];
+            canonical_weights(plan, coeffs + static_cast<int64_t>(g) * plan->npoints, w);
+            if (st_status r = run_steps(&one, c, grids[g], works[g], w, steps[g], s); r != ST_OK) return r;
+        }
+        return ST_OK;
+    }
+    // Per-grid pass lists; launch p covers every grid that still has a pass.
+    std::vector<std::vector<int>> passes(n);
+    std::vector<char> needs_copy(n, 0);
+    size_t npass = 0;
+    for (int g = 0; g < n; ++g) {
+        bool copy = false;
+        passes[g] = pass_list(steps[g], c.tb, copy);
+        needs_copy[g] = copy;
+        npass = std::max(npass, passes[g].size());
+    }
+    // Descriptor tables, one block of up to n entries per launch.
+    std::vector<Stream2DGrid> table;
+    std::vector<std::pair<size_t, int>> launches;  // (first entry, count)
+    std::vector<int64_t> items;
+    for (size_t pi = 0; pi < npass; ++pi) {
+        const size_t first = table.size();
+        int64_t begin = 0;
+        for (int g = 0; g < n; ++g) {
+            if (pi >= passes[g].size()) continue;
+            const int tb = passes[g][pi];
+            Geo2 geo;
+            if (!geo2(c, plan->grids[g].ny, plan->grids[g].nx, tb, geo))
+                return fail(ST_ERR_UNSUPPORTED, "2D tiling infeasible for grid %d", g);
+            Stream2DGrid G;
+            std::memset(&G, 0, sizeof(G));
+            const bool even = (pi % 2) == 0;
+            G.src = even ? grids[g] : works[g];
+            G.dst = even ? works[g] : grids[g];
+            G.ny = plan->grids[g].ny;
+            G.nx = plan->grids[g].nx;
+            G.tiles_x = geo.tiles_x;
+            G.chunks_y = geo.chunks_y;
+            G.chunk_y = geo.chunk_y;
+            G.out_w = geo.out_w;
+            G.hxa = geo.hxa;
+            G.vec_ok = (G.nx % c.k2.vx == 0) && aligned16(grids[g]) && aligned16(works[g]);
+            G.tb = tb;
+            G.tile_begin = begin;
+            canonical_weights(plan, coeffs + static_cast<int64_t>(g) * plan->npoints, G.w);
+            begin += geo.items;
+            table.push_back(G);
+        }
+        launches.emplace_back(first, static_cast<int>(table.size() - first));
+        items.push_back(begin);
+    }
+    const size_t need = table.size() * sizeof(Stream2DGrid);
+    if (need > plan->table_cap) {
+        if (stream_capturing(s)) return fail(ST_ERR_CAPTURE, "descriptor table growth during capture");
+        if (plan->table_pending) {
+            hipEventSynchronize(plan->table_done);
+            plan->table_pending = false;
+        }
+        if (plan->table_dev) hipFree(plan->table_dev);
+        if (plan->table_host) hipHostFree(plan->table_host);
+        plan->table_dev = plan->table_host = nullptr;
+        plan->table_cap = 0;
+        if (hipMalloc(&plan->table_dev, need) != hipSuccess ||
+            hipHostMalloc(&plan->table_host, need, hipHostMallocDefault) != hipSuccess)
+            return fail(ST_ERR_NOMEM, "descriptor table allocation (%zu bytes) failed", need);
+        plan->table_cap = need;
+        if (!plan->table_done) ST_HIP(hipEventCreateWithFlags(&plan->table_done, hipEventDisableTiming), "hipEventCreate");
+    }
+    if (plan->table_pending) {
+        // the previous call's upload may still read the pinned buffer
+        ST_HIP(hipEventSynchronize(plan->table_done), "hipEventSynchronize(table)");
+        plan->table_pending = false;
+    }
+    std::memcpy(plan->table_host, table.data(), need);
+    ST_HIP(hipMemcpyAsync(plan->table_dev, plan->table_host, need, hipMemcpyHostToDevice, s), "hipMemcpyAsync(table)");
+    ST_HIP(hipEventRecord(plan->table_done, s), "hipEventRecord(table)");
+    plan->table_pending = true;
+    const Stream2DGrid* dev = static_cast<const Stream2DGrid*>(plan->table_dev);
+    for (size_t pi = 0; pi < launches.size(); ++pi) {
+        Stream2DArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.grids = dev + launches[pi].first;
+        a.ngrids = launches[pi].second;
+        a.items = items[pi];
+        hipError_t e = launch_stream2d(c.k2, a, s);
+        if (e != hipSuccess) return hip_fail(e, "stream2d batch launch");
+    }
+    for (int g = 0; g < n; ++g) {
+        if (!needs_copy[g]) continue;
+        const size_t bytes = static_cast<size_t>(plan->grids[g].ny * plan->grids[g].nx) * elem_bytes(plan->dtype);
+        ST_HIP(hipMemcpyAsync(grids[g], works[g], bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(batch copy)");
+    }
+    return ST_OK;
+}

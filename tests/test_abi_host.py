@@ -1,0 +1,186 @@
+"""Host-side checks of libstencil.so: it loads, exports every declared symbol,
+classifies patterns, plans tilings, and rejects bad arguments before any
+launch.  No kernel runs here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2303_08365_amd as st
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x100000  # never dereferenced: every case below fails host-side checks
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", fn)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names.update(re.findall(r"\b(stencil_\w+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = st.library()
+    names = _declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert b"gfx950" in lib.stencil_version()
+
+
+def test_star_and_box_classification_and_families():
+    p = st.Plan(synth.star_offsets(3, 1), (64, 64, 64), "f64")
+    i = p.info()
+    assert i["kernel"] == st.KERNEL_STREAM3D and i["shape_class"] == 1 and i["radius"] == 1
+    p = st.Plan(synth.star_offsets(3, 4), (64, 64, 64), "f32", "periodic")
+    assert p.info()["radius"] == 4 and p.info()["kernel"] == st.KERNEL_STREAM3D
+    p = st.Plan(synth.box_offsets(2, 1), (100, 300), "f32")
+    assert p.info()["shape_class"] == 2 and p.info()["kernel"] == st.KERNEL_STREAM2D
+    p = st.Plan(synth.star_offsets(2, 1), (100, 300), "bf16")
+    assert p.info()["kernel"] == st.KERNEL_STREAM2D
+    # general point sets and 3D boxes run on the one-step kernel
+    p = st.Plan([(0, 0), (0, 1), (-2, 0)], (50, 50), "f64")
+    assert p.info()["shape_class"] == 0 and p.info()["kernel"] == st.KERNEL_NAIVE
+    p = st.Plan(synth.box_offsets(3, 1), (20, 20, 20), "f64")
+    assert p.info()["shape_class"] == 2 and p.info()["kernel"] == st.KERNEL_NAIVE
+    p = st.Plan(synth.star_offsets(1, 2), (1000,), "f64")
+    assert p.info()["kernel"] == st.KERNEL_NAIVE
+    p = st.Plan(synth.star_offsets(3, 1), (64, 64, 64), "f64", naive=True)
+    assert p.info()["kernel"] == st.KERNEL_NAIVE and p.info()["ncandidates"] == 1
+
+
+def test_candidates_and_select():
+    p = st.Plan(synth.star_offsets(3, 1), (512, 512, 512), "f64")
+    cands = p.candidates()
+    assert len(cands) >= 3 and cands[-1]["kernel"] == st.KERNEL_NAIVE
+    for c in cands:
+        assert c["workgroups"] > 0 and c["tile_x"] > 0
+    tb2 = [k for k, c in enumerate(cands) if c["tb"] == 2]
+    assert tb2
+    p.select(variant=tb2[0])
+    assert p.info()["tb"] == 2 and p.info()["variant"] == tb2[0]
+    p.select(kernel=st.KERNEL_NAIVE)
+    assert p.info()["kernel"] == st.KERNEL_NAIVE
+    with pytest.raises(st.StencilError) as e:
+        p.select(variant=len(cands))
+    assert e.value.status == -2
+    with pytest.raises(st.StencilError):
+        p.select(kernel=st.KERNEL_STREAM2D)
+
+
+def test_fused_tiles_shrink_by_the_halo():
+    p = st.Plan(synth.star_offsets(2, 1), (4096, 4096), "f32")
+    by_tb = {c["tb"]: c for c in p.candidates() if c["kernel"] == st.KERNEL_STREAM2D}
+    assert by_tb[1]["tile_x"] == 256            # 64 lanes x 4 columns, no halo
+    assert by_tb[8]["tile_x"] == 256 - 2 * 8    # halo 7 rounded up to the lane width
+
+
+def _raw_plan(offsets, shape, dtype=0, bc=0, flags=0):
+    lib = st.library()
+    pat, keep = st._pattern(offsets)
+    shp = (ctypes.c_int64 * len(shape))(*shape)
+    h = ctypes.c_void_p()
+    rc = lib.stencil_plan(ctypes.byref(h), ctypes.byref(pat), shp, dtype, bc, flags)
+    return rc, h, keep
+
+
+@pytest.mark.parametrize("offsets,shape,dtype,bc,flags,code", [
+    ([(0, 0), (0, 1)], (0, 5), 0, 0, 0, -1),                 # zero extent
+    ([(0, 1), (1, 0)], (5, 5), 0, 0, 0, -1),                 # no centre
+    ([(0, 0), (0, 5)], (9, 9), 0, 0, 0, -2),                 # radius 5
+    ([(0, 0), (0, 1), (0, 1)], (9, 9), 0, 0, 0, -1),         # repeated point
+    ([(0, 0)], (9, 9), 7, 0, 0, -1),                         # bad dtype
+    ([(0, 0)], (9, 9), 0, 3, 0, -1),                         # bad boundary
+    ([(0, 0)], (9, 9), 0, 0, 0x80, -1),                      # unknown flag
+    ([(0, 0, 0, 0)], (2, 2, 2, 2), 0, 0, 0, -2),             # 4D
+])
+def test_plan_rejects(offsets, shape, dtype, bc, flags, code):
+    rc, h, _ = _raw_plan(offsets, shape, dtype, bc, flags)
+    assert rc == code
+    assert not h.value
+    assert st.library().stencil_last_error()
+
+
+def test_plan_rejects_null_and_too_many_points():
+    lib = st.library()
+    h = ctypes.c_void_p()
+    shp = (ctypes.c_int64 * 2)(5, 5)
+    assert lib.stencil_plan(ctypes.byref(h), None, shp, 0, 0, 0) == -1
+    pat, keep = st._pattern(synth.box_offsets(3, 2) + [(3, 3, 3)])  # 126 points
+    assert lib.stencil_plan(ctypes.byref(h), ctypes.byref(pat), (ctypes.c_int64 * 3)(9, 9, 9), 0, 0, 0) == -2
+
+
+def test_run_rejects_bad_arguments_before_launch():
+    lib = st.library()
+    rc, h, keep = _raw_plan(synth.star_offsets(2, 1), (40, 50))
+    assert rc == 0
+    w = (ctypes.c_double * 5)(*synth.heat_weights(2, 0.1))
+    good = (ctypes.c_int64 * 2)(40, 50)
+    bad = (ctypes.c_int64 * 2)(40, 51)
+    P = ctypes.c_void_p
+    assert lib.stencil_run(h, P(FAKE), P(FAKE + 64), w, bad, 3, 0, None) == -3      # shape
+    assert lib.stencil_run(h, P(FAKE), P(FAKE + 64), w, good, 3, 1, None) == -3     # boundary
+    assert lib.stencil_run(h, P(FAKE), P(FAKE + 64), w, good, -1, 0, None) == -1    # steps < 0
+    assert lib.stencil_run(h, None, P(FAKE), w, good, 3, 0, None) == -1             # no grid
+    assert lib.stencil_run(h, P(FAKE), P(FAKE + 64), None, good, 3, 0, None) == -1  # no coeffs
+    nanw = (ctypes.c_double * 5)(1.0, float("nan"), 0, 0, 0)
+    assert lib.stencil_run(h, P(FAKE), P(FAKE + 64), nanw, good, 3, 0, None) == -1
+    # zero steps is a no-op that touches nothing
+    assert lib.stencil_run(h, P(FAKE), P(FAKE + 64), w, good, 0, 0, None) == 0
+    assert lib.stencil_run(None, P(FAKE), P(FAKE + 64), w, good, 3, 0, None) == -1
+    lib.stencil_plan_destroy(h)
+    assert lib.stencil_plan_destroy(None) == 0
+
+
+def test_batch_plan_and_run_validation():
+    lib = st.library()
+    shapes = [(37, 300), (256, 1000), (1024, 77)]
+    bp = st.BatchPlan(synth.star_offsets(2, 1), shapes, "f32")
+    assert bp.info()["kernel"] == st.KERNEL_STREAM2D
+    P = ctypes.c_void_p
+    grids = (P * 3)(FAKE, FAKE + 4096, FAKE + 8192)
+    works = (P * 3)(FAKE + 64, FAKE + 4096 + 64, FAKE + 8192 + 64)
+    cf = (ctypes.c_double * 15)(*(list(synth.heat_weights(2, 0.1)) * 3))
+    steps = (ctypes.c_int64 * 3)(5, 5, 5)
+    assert lib.stencil_batch_run(bp._h, 2, grids, works, cf, steps, None) == -3
+    neg = (ctypes.c_int64 * 3)(5, -1, 5)
+    assert lib.stencil_batch_run(bp._h, 3, grids, works, cf, neg, None) == -1
+    same = (P * 3)(FAKE, FAKE + 4096, FAKE + 8192)
+    assert lib.stencil_batch_run(bp._h, 3, grids, same, cf, steps, None) == -1
+    zero = (ctypes.c_int64 * 3)(0, 0, 0)
+    assert lib.stencil_batch_run(bp._h, 3, grids, works, cf, zero, None) == 0
+    # 3D and general patterns are not batched
+    with pytest.raises(st.StencilError):
+        st.BatchPlan(synth.star_offsets(3, 1), [(8, 8)], "f32")
+    with pytest.raises(st.StencilError):
+        st.BatchPlan([(0, 0), (1, 2)], [(8, 8)], "f32")
+    # single-grid and batch plans are not interchangeable
+    rc, h, keep = _raw_plan(synth.star_offsets(2, 1), (40, 50))
+    assert lib.stencil_batch_run(h, 1, grids, works, cf, steps, None) == -3
+    lib.stencil_plan_destroy(h)
+
+
+def _gpu_present():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the no-device error path")
+def test_run_without_device_reports_hip_error():
+    lib = st.library()
+    rc, h, keep = _raw_plan(synth.star_offsets(2, 1), (40, 50))
+    w = (ctypes.c_double * 5)(*synth.heat_weights(2, 0.1))
+    good = (ctypes.c_int64 * 2)(40, 50)
+    P = ctypes.c_void_p
+    assert lib.stencil_run(h, P(FAKE), P(FAKE + 64), w, good, 3, 0, None) == -5
+    assert b"hipGetDeviceCount" in lib.stencil_last_error()
+    lib.stencil_plan_destroy(h)
