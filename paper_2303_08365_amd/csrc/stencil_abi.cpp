@@ -268,7 +268,7 @@ void build_candidates(st_plan_s* p) {
                     Candidate c;
                     c.kernel = ST_KERNEL_STREAM3D;
                     c.tb = tb;
-                    c.k3 = Stream3DKey{p->dtype, p->bc, p->radius, tbmax, v.vx, v.k, v.nw};
+                    c.k3 = Stream3DKey{p->dtype, p->bc, p->radius, tbmax, v.vx, v.k, v.nw, 1};
                     Geo3 g;
                     if (stream3d_has(c.k3) && geo3(c, p->n, tb, g)) {
                         fast.push_back(c);
@@ -277,7 +277,8 @@ void build_candidates(st_plan_s* p) {
                 }
             }
         }
-        const int want = 1;
+        // measured on MI355X (512^3): two fused steps beat one for radius 1
+        const int want = p->radius == 1 ? 2 : 1;
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
             return (a.tb == want) > (b.tb == want);
         });
@@ -441,7 +442,10 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
     if (c.kernel == ST_KERNEL_STREAM3D) {
         Geo3 g;
         if (!geo3(c, p->n, tb, g)) return fail(ST_ERR_UNSUPPORTED, "3D tiling infeasible");
-        const int lds = stream3d_lds_bytes(c.k3);
+        Stream3DKey key = c.k3;
+        key.fast = vec_ok && (p->bc == kPeriodic ||
+                              (p->n[2] >= 64 * key.vx && p->n[1] >= static_cast<int64_t>(key.k) * key.nw));
+        const int lds = stream3d_lds_bytes(key);
         if (lds > device_lds_limit())
             return fail(ST_ERR_UNSUPPORTED, "tiling needs %d bytes of LDS, the device allows %d", lds,
                         device_lds_limit());
@@ -463,7 +467,7 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
         a.vec_ok = vec_ok ? 1 : 0;
         a.tb = tb;
         for (int i = 0; i < p->npoints; ++i) a.w[i] = wcan[i];
-        e = launch_stream3d(c.k3, a, s);
+        e = launch_stream3d(key, a, s);
         if (e != hipSuccess) return hip_fail(e, "stream3d launch");
         return ST_OK;
     }

@@ -3,25 +3,36 @@
 // 2.5-D blocking: an xy tile is held on chip while the work-group streams
 // along z (paper Sec. 4.1 builds space-time tiles, tetrahedra in 3D; Sec. 4.2
 // stages tiles on chip so global accesses stay coalesced).  On gfx950 the
-// on-chip tile lives mostly in VGPRs:
+// on-chip tile lives in VGPRs:
 //   * lane L of wave w holds columns X0 + L*VX .. +VX-1 of rows
-//     Y0 + w*K .. Y0 + w*K + K-1 of every plane (one 16-byte access per row);
+//     Y0 + w*K .. Y0 + w*K + K-1 (one 16-byte access per row);
 //   * pipeline level l keeps the last 2R+1 planes of step l (its z queue);
-//   * x neighbours: own registers, or lane +-1 through DPP (the outermost R
-//     columns of step 0 are loaded by lanes 0 and 63 and enter through the
-//     DPP "old" operand);
-//   * y neighbours: own rows, or the R edge rows of the wave above / below,
-//     exchanged through LDS once per level and plane (the R rows above and
-//     below the whole tile, for step 0, are loaded by the first / last wave);
+//   * x neighbours: own registers, or lane +-1 through DPP.  The R columns
+//     just outside the tile (step 0 only) are fetched for all K rows by one
+//     load instruction (lanes 0.. and 32.. each fetch one value) and enter the
+//     DPP "old" operand of lanes 0 and 63 through readlane;
+//   * y neighbours of step 0: own rows, plus R rows above and R rows below
+//     the wave's rows loaded directly (they are other waves' rows, so the
+//     loads hit in cache); of steps >= 1 (T_b > 1): the edge rows of the
+//     neighbouring waves, exchanged through LDS once per level and plane;
 //   * z neighbours: queue slots.
-// Step l is exact on the register tile shrunk by (l-1)*R on each side; the
-// tile interior [X0+hxa, X0+W-hxa) x [Y0+hya, Y0+H-hya), hxa, hya >=
-// R*(tb-1), is stored.  A z chunk [zs, ze) loads planes zs-R*tb .. ze-1+R*tb.
+// Loads run P planes ahead of use (P = 3 when 2R+1 is a multiple of 3) and
+// are unconditional: ghost cells (zero rule) are replaced by 0 with selects
+// when the values are consumed, so no branch separates a load from its use
+// and the prefetch stays in flight.
 //
-// LDS (per buffer, two buffers alternate between barriers): tile rows
-// -R .. H+R-1 of the plane being advanced; each wave publishes only the rows
-// other waves read (its first R and last R rows), and the first / last wave
-// the ring rows.
+// Tiles.  Step l is exact on the register tile shrunk by (l-1)*R per side
+// (hxa, hya >= R*(tb-1) columns/rows of halo are stored by the neighbour
+// tile).  Under the zero rule a tile that would cross the grid edge is moved
+// inward to touch it instead: the ghost layer outside the grid is 0 at every
+// step (lanes 0/63 get 0 from DPP, the LDS ring rows hold 0), so the tile
+// stays exact up to the edge.  Under the periodic rule tiles keep their
+// place and every index wraps.  A z chunk [zs, ze) streams planes
+// zs - R*tb .. ze - 1 + R*tb.
+//
+// FAST = whole-vector row access (nx % VX == 0, 16-byte aligned base, and
+// under the zero rule nx >= 64*VX, ny >= NW*K); otherwise every element is
+// loaded and stored on its own, with the same arithmetic.
 #pragma once
 
 #include <utility>
@@ -33,127 +44,113 @@ namespace st {
 
 namespace s3d {
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST>
 struct Kern {
     using S = Storage<TS>;
     using TC = typename S::TC;
     static_assert(VX >= R, "a lane must hold at least R columns");
+    static_assert(K * R <= 32, "the x ring of a wave must fit in half a wave");
     static constexpr int Q = 2 * R + 1;
+    static constexpr int P = (Q % 3 == 0) ? 3 : Q;       // main-plane prefetch depth
+    static constexpr int PR = (R == 1) ? P : 1;          // ring prefetch depth
     static constexpr int W = 64 * VX;
     static constexpr int H = NW * K;
     static constexpr int NP = 6 * R + 1;
-    // LDS row slot of tile row r (-R <= r < H + R) is r + R.
-    static constexpr int SLOTS = H + 2 * R;
+    static constexpr int SLOTS = H + 2 * R;              // LDS rows -R .. H+R-1
     static constexpr int BUF_ELEMS = SLOTS * W;
-    static constexpr int LDS_BYTES = 2 * BUF_ELEMS * static_cast<int>(sizeof(TC));
+    static constexpr int LDS_BYTES = TBMAX > 1 ? 2 * BUF_ELEMS * static_cast<int>(sizeof(TC)) : 0;
 
     struct Ctx {
         const TS* src;
         TS* dst;
         int64_t nz, ny, nx;
         int64_t X0, Y0;
-        int64_t xl;           // first column of this lane
-        int64_t yw;           // first row of this wave
-        int64_t zs, ze;
-        int64_t ox0, ox1, oy0, oy1;   // output columns / rows
-        bool fast;
+        int64_t xl;            // first column of this lane
+        int64_t yw;            // first row of this wave
+        int64_t zs, ze, zlast; // output planes [zs, ze); last streamed plane
+        int64_t ox0, ox1, oy0, oy1;
+        int64_t xr_x, xr_y;    // the x-ring element this lane fetches
         int lane, wave;
         TC w[NP];
     };
 
-    static __device__ __forceinline__ int64_t plane_idx(const Ctx& c, int64_t z, bool& ghost) {
-        ghost = false;
-        if (z < 0 || z >= c.nz) {
-            if (!PER) { ghost = true; return 0; }
-            z = wrap_idx(z, c.nz);
-        }
-        return z;
+    // index rules: periodic wraps, zero clamps (the value is then masked)
+    static __device__ __forceinline__ int64_t fix(int64_t i, int64_t n) {
+        if (PER) return wrap_idx(i, n);
+        return i < 0 ? 0 : (i >= n ? n - 1 : i);
+    }
+    static __device__ __forceinline__ bool ghost(int64_t i, int64_t n) {
+        return !PER && (i < 0 || i >= n);
     }
 
-    // One row (x strip of this lane) of plane z, row y.
-    static __device__ __forceinline__ void load_row(const Ctx& c, int64_t z, bool zghost, int64_t y,
-                                                    TC (&v)[VX]) {
-        bool ghost = zghost;
-        if (y < 0 || y >= c.ny) {
-            if (!PER) ghost = true; else y = wrap_idx(y, c.ny);
-        }
-        if (ghost) {
-#pragma unroll
-            for (int e = 0; e < VX; ++e) v[e] = TC(0);
-            return;
-        }
-        const TS* row = c.src + (z * c.ny + y) * c.nx;
-        if (c.fast) {
-            ldv<TS, VX>(row + c.xl, v);
+    static __device__ __forceinline__ void load_row(const Ctx& c, int64_t zz, int64_t y, TC (&v)[VX]) {
+        const TS* row = c.src + (zz * c.ny + fix(y, c.ny)) * c.nx;
+        if constexpr (FAST) {
+            ldv<TS, VX>(row + (PER ? wrap_idx(c.xl, c.nx) : c.xl), v);
         } else {
 #pragma unroll
-            for (int e = 0; e < VX; ++e) {
-                const int64_t x = c.xl + e;
-                if (PER) v[e] = ld1(row + wrap_idx(x, c.nx));
-                else v[e] = (x >= 0 && x < c.nx) ? ld1(row + x) : TC(0);
-            }
+            for (int e = 0; e < VX; ++e) v[e] = ld1(row + fix(c.xl + e, c.nx));
         }
     }
 
-    static __device__ __forceinline__ void load_plane(const Ctx& c, int64_t z, TC (&v)[K][VX]) {
-        bool zg;
-        const int64_t zz = plane_idx(c, z, zg);
+    // Loads of one pipeline slot: the wave's K rows of plane zm, and the ring
+    // (2R rows, one x-ring value per lane) of plane zr.
+    static __device__ __forceinline__ void load_main(const Ctx& c, int64_t zm, TC (&v)[K][VX]) {
+        const int64_t zz = fix(zm < c.zlast ? zm : c.zlast, c.nz);
 #pragma unroll
-        for (int k = 0; k < K; ++k) load_row(c, zz, zg, c.yw + k, v[k]);
+        for (int k = 0; k < K; ++k) load_row(c, zz, c.yw + k, v[k]);
+    }
+    static __device__ __forceinline__ void load_ring(const Ctx& c, int64_t zr, TC (&r)[2 * R][VX], TC& xv) {
+        const int64_t zz = fix(zr < c.zlast ? zr : c.zlast, c.nz);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            load_row(c, zz, c.yw - R + j, r[j]);
+            load_row(c, zz, c.yw + K + j, r[R + j]);
+        }
+        xv = ld1(c.src + (zz * c.ny + fix(c.xr_y, c.ny)) * c.nx + fix(c.xr_x, c.nx));
     }
 
-    // x ring (lanes 0 and 63) for this wave's rows of plane z.
-    static __device__ __forceinline__ void load_xring(const Ctx& c, int64_t z, TC (&r)[K][R]) {
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int j = 0; j < R; ++j) r[k][j] = TC(0);
-        if (c.lane != 0 && c.lane != 63) return;
-        bool zg;
-        const int64_t zz = plane_idx(c, z, zg);
-        if (zg) return;
-        const int64_t xb = (c.lane == 0) ? c.X0 - R : c.X0 + W;
+    // Ghost masks applied when a slot is consumed.
+    static __device__ __forceinline__ void take_main(const Ctx& c, int64_t z, const TC (&v)[K][VX],
+                                                     TC (&q)[K][VX]) {
+        const bool zg = ghost(z, c.nz);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            int64_t y = c.yw + k;
-            if (y < 0 || y >= c.ny) {
-                if (!PER) continue;
-                y = wrap_idx(y, c.ny);
-            }
-            const TS* row = c.src + (zz * c.ny + y) * c.nx;
+            const bool rg = zg || (!FAST && ghost(c.yw + k, c.ny));
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const int64_t x = xb + j;
-                if (PER) r[k][j] = ld1(row + wrap_idx(x, c.nx));
-                else r[k][j] = (x >= 0 && x < c.nx) ? ld1(row + x) : TC(0);
+            for (int e = 0; e < VX; ++e) {
+                const bool g = rg || (!FAST && ghost(c.xl + e, c.nx));
+                q[k][e] = g ? TC(0) : v[k][e];
             }
         }
     }
-
-    // y ring: R rows above the tile (first wave) or below it (last wave).
-    static __device__ __forceinline__ void load_yring(const Ctx& c, int64_t z, TC (&top)[R][VX],
-                                                      TC (&bot)[R][VX]) {
-        bool zg;
-        const int64_t zz = plane_idx(c, z, zg);
-        if (c.wave == 0) {
+    static __device__ __forceinline__ void take_ring(const Ctx& c, int64_t z, const TC (&r)[2 * R][VX],
+                                                     TC xv, TC (&above)[R][VX], TC (&below)[R][VX],
+                                                     TC& xg) {
+        const bool zg = ghost(z, c.nz);
 #pragma unroll
-            for (int j = 0; j < R; ++j) load_row(c, zz, zg, c.Y0 - R + j, top[j]);
-        }
-        if (c.wave == NW - 1) {
+        for (int j = 0; j < R; ++j) {
+            const bool ga = zg || ghost(c.yw - R + j, c.ny);
+            const bool gb = zg || ghost(c.yw + K + j, c.ny);
 #pragma unroll
-            for (int j = 0; j < R; ++j) load_row(c, zz, zg, c.Y0 + H + j, bot[j]);
+            for (int e = 0; e < VX; ++e) {
+                const bool xe = !FAST && ghost(c.xl + e, c.nx);
+                above[j][e] = (ga || xe) ? TC(0) : r[j][e];
+                below[j][e] = (gb || xe) ? TC(0) : r[R + j][e];
+            }
         }
+        xg = (zg || ghost(c.xr_y, c.ny) || ghost(c.xr_x, c.nx)) ? TC(0) : xv;
     }
 
-    static __device__ __forceinline__ void lds_put(TC* buf, int slot, int lane, const TC (&v)[VX]) {
-        TC* p = buf + slot * W + lane * VX;
-#pragma unroll
-        for (int e = 0; e < VX; ++e) p[e] = v[e];
-    }
-    static __device__ __forceinline__ void lds_get(const TC* buf, int slot, int lane, TC (&v)[VX]) {
-        const TC* p = buf + slot * W + lane * VX;
-#pragma unroll
-        for (int e = 0; e < VX; ++e) v[e] = p[e];
+    static __device__ __forceinline__ TC lane_value(TC v, int src_lane) {
+        if constexpr (sizeof(TC) == 8) {
+            const uint64_t b = __double_as_longlong(v);
+            const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(b), src_lane);
+            const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), src_lane);
+            return __longlong_as_double((static_cast<uint64_t>(hi) << 32) | lo);
+        } else {
+            return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src_lane));
+        }
     }
 
     static __device__ __forceinline__ TC xval(const TC (&v)[VX], const TC (&lft)[R],
@@ -161,21 +158,23 @@ struct Kern {
         return idx < 0 ? lft[R + idx] : (idx >= VX ? rgt[idx - VX] : v[idx]);
     }
 
-    // Step l+1 on plane (newest - R) from the queue of step l.  Canonical point
-    // order for a 3D star: centre; z -R..-1; y -R..-1; x -R..-1; x +1..+R;
-    // y +1..+R; z +1..+R.
-    template <int J>
-    static __device__ __forceinline__ void compute(const Ctx& c, const TC (&q)[Q][K][VX],
-                                                   const TC (&xr)[K][R], const TC (&above)[R][VX],
-                                                   const TC (&below)[R][VX], TC (&out)[K][VX]) {
+    // Step l+1 on the centre plane of queue q (slot (J-R) mod Q).  Canonical
+    // point order for a 3D star: centre; z -R..-1; y -R..-1; x -R..-1;
+    // x +1..+R; y +1..+R; z +1..+R.
+    template <int J, bool LEVEL0>
+    static __device__ __forceinline__ void compute(const Ctx& c, const TC (&q)[Q][K][VX], TC xg,
+                                                   const TC (&above)[R][VX], const TC (&below)[R][VX],
+                                                   TC (&out)[K][VX]) {
         constexpr int CEN = (J - R + Q) % Q;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             TC lft[R], rgt[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                lft[j] = from_lower(q[CEN][k][VX - R + j], xr[k][j]);
-                rgt[j] = from_upper(q[CEN][k][j], xr[k][j]);
+                const TC ol = LEVEL0 ? lane_value(xg, k * R + j) : TC(0);
+                const TC orr = LEVEL0 ? lane_value(xg, 32 + k * R + j) : TC(0);
+                lft[j] = from_lower(q[CEN][k][VX - R + j], ol);
+                rgt[j] = from_upper(q[CEN][k][j], orr);
             }
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
@@ -210,115 +209,87 @@ struct Kern {
         }
     }
 
+    // Zero rule: ghost cells stay 0; bfloat16 storage rounds every step.
     static __device__ __forceinline__ void finish(const Ctx& c, int64_t z, TC (&out)[K][VX]) {
-        if (!PER) {
-            const bool zg = z < 0 || z >= c.nz;
+        const bool zg = ghost(z, c.nz);
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int64_t y = c.yw + k;
-                const bool rowg = zg || y < 0 || y >= c.ny;
+        for (int k = 0; k < K; ++k) {
+            const bool rg = zg || (!FAST && ghost(c.yw + k, c.ny));
 #pragma unroll
-                for (int e = 0; e < VX; ++e) {
-                    const int64_t x = c.xl + e;
-                    if (rowg || (!c.fast && (x < 0 || x >= c.nx))) out[k][e] = TC(0);
-                }
+            for (int e = 0; e < VX; ++e) {
+                const bool g = rg || (!FAST && ghost(c.xl + e, c.nx));
+                out[k][e] = g ? TC(0) : S::round(out[k][e]);
             }
         }
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int e = 0; e < VX; ++e) out[k][e] = S::round(out[k][e]);
     }
 
     static __device__ __forceinline__ void store_plane(const Ctx& c, int64_t z, const TC (&out)[K][VX]) {
         if (z < c.zs || z >= c.ze) return;
-        if (c.xl < c.ox0 || c.xl >= c.ox1) return;
+        if (c.xl < c.ox0 || c.xl >= c.ox1) return;  // lanes are wholly in or out
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int64_t y = c.yw + k;
-            if (y < c.oy0 || y >= c.oy1 || y >= c.ny) continue;
+            if (y < c.oy0 || y >= c.oy1) continue;
             TS* row = c.dst + (z * c.ny + y) * c.nx;
-            if (c.fast) {
+            if constexpr (FAST) {
                 stv<TS, VX>(row + c.xl, out[k]);
             } else {
 #pragma unroll
-                for (int e = 0; e < VX; ++e) {
-                    const int64_t x = c.xl + e;
-                    if (x < c.nx) st1(row + x, out[k][e]);
-                }
+                for (int e = 0; e < VX; ++e)
+                    if (c.xl + e < c.nx) st1(row + c.xl + e, out[k][e]);
             }
         }
     }
 
     struct State {
         TC q[TBMAX][Q][K][VX];
-        TC pf[K][VX];
-        TC xr[K][R], nxr[K][R];
-        TC top[R][VX], bot[R][VX], ntop[R][VX], nbot[R][VX];
+        TC pf[P][K][VX];
+        TC rpf[PR][2 * R][VX];
+        TC xpf[PR];
     };
 
     template <int J>
-    static __device__ __forceinline__ void step(const Ctx& c, int tb, int64_t it, int64_t nit,
-                                                int64_t zfirst, State& s, TC* lds) {
+    static __device__ __forceinline__ void step(const Ctx& c, int tb, int64_t it, int64_t zfirst, State& s,
+                                                TC* lds) {
+        constexpr int SM = J % P, SR = J % PR;
         const int64_t zin = zfirst + it;
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int e = 0; e < VX; ++e) s.q[0][J][k][e] = s.pf[k][e];
-        // rings of the step-0 centre plane (zin - R) were fetched last iteration
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int j = 0; j < R; ++j) s.xr[k][j] = s.nxr[k][j];
-#pragma unroll
-        for (int j = 0; j < R; ++j)
-#pragma unroll
-            for (int e = 0; e < VX; ++e) {
-                s.top[j][e] = s.ntop[j][e];
-                s.bot[j][e] = s.nbot[j][e];
-            }
-        if (it + 1 < nit) {
-            load_plane(c, zin + 1, s.pf);
-            load_xring(c, zin + 1 - R, s.nxr);
-            load_yring(c, zin + 1 - R, s.ntop, s.nbot);
-        }
+        // consume this iteration's slots, then refill them P (PR) planes ahead
+        take_main(c, zin, s.pf[SM], s.q[0][J]);
+        TC above0[R][VX], below0[R][VX], xg;
+        take_ring(c, zin - R, s.rpf[SR], s.xpf[SR], above0, below0, xg);
+        load_main(c, zin + P, s.pf[SM]);
+        load_ring(c, zin + PR - R, s.rpf[SR], s.xpf[SR]);
+
         constexpr int CEN = (J - R + Q) % Q;
 #pragma unroll
         for (int l = 0; l < TBMAX; ++l) {
             if (l < tb) {
-                TC* buf = lds + ((it * tb + l) & 1) * BUF_ELEMS;
-                // publish the rows of the centre plane that other waves read
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    if (k < R || k >= K - R) lds_put(buf, c.wave * K + k + R, c.lane, s.q[l][CEN][k]);
-                }
-                if (l == 0) {
-                    if (c.wave == 0) {
-#pragma unroll
-                        for (int j = 0; j < R; ++j) lds_put(buf, j, c.lane, s.top[j]);
-                    }
-                    if (c.wave == NW - 1) {
-#pragma unroll
-                        for (int j = 0; j < R; ++j) lds_put(buf, H + R + j, c.lane, s.bot[j]);
-                    }
-                }
-                __syncthreads();
-                TC above[R][VX], below[R][VX];
-#pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    lds_get(buf, c.wave * K + j, c.lane, above[j]);          // row wK - R + j
-                    lds_get(buf, c.wave * K + K + R + j, c.lane, below[j]);  // row wK + K + j
-                }
                 TC out[K][VX];
                 if (l == 0) {
-                    compute<J>(c, s.q[0], s.xr, above, below, out);
+                    compute<J, true>(c, s.q[0], xg, above0, below0, out);
                 } else {
-                    TC zr[K][R];
+                    TC* buf = lds + ((it * (tb - 1) + (l - 1)) & 1) * BUF_ELEMS;
 #pragma unroll
-                    for (int k = 0; k < K; ++k)
+                    for (int k = 0; k < K; ++k) {
+                        if (k < R || k >= K - R) {
+                            TC* p = buf + (c.wave * K + k + R) * W + c.lane * VX;
 #pragma unroll
-                        for (int j = 0; j < R; ++j) zr[k][j] = TC(0);
-                    compute<J>(c, s.q[l], zr, above, below, out);
+                            for (int e = 0; e < VX; ++e) p[e] = s.q[l][CEN][k][e];
+                        }
+                    }
+                    __syncthreads();
+                    TC above[R][VX], below[R][VX];
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        const TC* pa = buf + (c.wave * K + j) * W + c.lane * VX;
+                        const TC* pb = buf + (c.wave * K + K + R + j) * W + c.lane * VX;
+#pragma unroll
+                        for (int e = 0; e < VX; ++e) {
+                            above[j][e] = pa[e];
+                            below[j][e] = pb[e];
+                        }
+                    }
+                    compute<J, false>(c, s.q[l], TC(0), above, below, out);
                 }
                 const int64_t zc = zin - static_cast<int64_t>(l + 1) * R;
                 finish(c, zc, out);
@@ -335,10 +306,14 @@ struct Kern {
     }
 
     template <int... J>
-    static __device__ __forceinline__ void unroll_steps(const Ctx& c, int tb, int64_t base, int64_t nit,
-                                                        int64_t zfirst, State& s, TC* lds,
-                                                        std::integer_sequence<int, J...>) {
-        ((base + J < nit ? step<J>(c, tb, base + J, nit, zfirst, s, lds) : void()), ...);
+    static __device__ __forceinline__ void group(const Ctx& c, int tb, int64_t base, int64_t zfirst, State& s,
+                                                 TC* lds, std::integer_sequence<int, J...>) {
+        (step<J>(c, tb, base + J, zfirst, s, lds), ...);
+    }
+    template <int... J>
+    static __device__ __forceinline__ void tail(const Ctx& c, int tb, int64_t base, int64_t nit, int64_t zfirst,
+                                                State& s, TC* lds, std::integer_sequence<int, J...>) {
+        ((base + J < nit ? step<J>(c, tb, base + J, zfirst, s, lds) : void()), ...);
     }
 
     static __device__ void run(const Stream3DArgs& a, TC* lds) {
@@ -356,23 +331,45 @@ struct Kern {
         c.nz = a.nz;
         c.ny = a.ny;
         c.nx = a.nx;
-        c.X0 = tx * a.out_w - a.hxa;
-        c.Y0 = ty * a.out_h - a.hya;
+        c.ox0 = tx * a.out_w;
+        c.oy0 = ty * a.out_h;
+        c.ox1 = c.ox0 + a.out_w < c.nx ? c.ox0 + a.out_w : c.nx;
+        c.oy1 = c.oy0 + a.out_h < c.ny ? c.oy0 + a.out_h : c.ny;
+        c.X0 = c.ox0 - a.hxa;
+        c.Y0 = c.oy0 - a.hya;
+        if (!PER && FAST) {  // move edge tiles inward (exact: the ghost layer is 0)
+            c.X0 = c.X0 < 0 ? 0 : (c.X0 + W > c.nx ? c.nx - W : c.X0);
+            c.Y0 = c.Y0 < 0 ? 0 : (c.Y0 + H > c.ny ? c.ny - H : c.Y0);
+        }
         c.xl = c.X0 + static_cast<int64_t>(c.lane) * VX;
         c.yw = c.Y0 + static_cast<int64_t>(c.wave) * K;
+        {
+            const bool right = c.lane >= 32;
+            const int slot = right ? c.lane - 32 : c.lane;
+            const int kr = slot < K * R ? slot / R : 0;
+            const int jr = slot < K * R ? slot % R : 0;
+            c.xr_y = c.yw + kr;
+            c.xr_x = right && slot < K * R ? c.X0 + W + jr : c.X0 - R + jr;
+        }
         c.zs = cz * a.chunk_z;
         c.ze = c.zs + a.chunk_z < c.nz ? c.zs + a.chunk_z : c.nz;
-        c.ox0 = c.X0 + a.hxa;
-        c.ox1 = c.ox0 + a.out_w;
-        c.oy0 = c.Y0 + a.hya;
-        c.oy1 = c.oy0 + a.out_h;
-        c.fast = a.vec_ok && c.X0 - R >= 0 && c.X0 + W + R <= c.nx && c.Y0 - R >= 0 &&
-                 c.Y0 + H + R <= c.ny;
 #pragma unroll
         for (int p = 0; p < NP; ++p) c.w[p] = static_cast<TC>(a.w[p]);
         const int tb = a.tb;
         const int64_t zfirst = c.zs - static_cast<int64_t>(R) * tb;
         const int64_t nit = (c.ze - c.zs) + 2 * static_cast<int64_t>(R) * tb;
+        c.zlast = zfirst + nit - 1;
+
+        if constexpr (TBMAX > 1) {
+            // ring rows of every LDS buffer stay 0 (ghost / unused halo)
+            for (int i = threadIdx.x; i < 2 * R * W; i += blockDim.x) {
+                const int row = i / W, col = i % W;
+                const int slot = row < R ? row : H + row;
+                lds[slot * W + col] = TC(0);
+                lds[BUF_ELEMS + slot * W + col] = TC(0);
+            }
+            __syncthreads();
+        }
 
         State s;
 #pragma unroll
@@ -384,47 +381,46 @@ struct Kern {
 #pragma unroll
                     for (int e = 0; e < VX; ++e) s.q[l][sl][k][e] = TC(0);
 #pragma unroll
-        for (int j = 0; j < R; ++j)
+        for (int sp = 0; sp < P; ++sp) load_main(c, zfirst + sp, s.pf[sp]);
 #pragma unroll
-            for (int e = 0; e < VX; ++e) s.ntop[j][e] = s.nbot[j][e] = TC(0);
-        load_plane(c, zfirst, s.pf);
-        load_xring(c, zfirst - R, s.nxr);
-        load_yring(c, zfirst - R, s.ntop, s.nbot);
-        for (int64_t base = 0; base < nit; base += Q)
-            unroll_steps(c, tb, base, nit, zfirst, s, lds, std::make_integer_sequence<int, Q>{});
+        for (int sp = 0; sp < PR; ++sp) load_ring(c, zfirst + sp - R, s.rpf[sp], s.xpf[sp]);
+
+        int64_t base = 0;
+        for (; base + Q <= nit; base += Q)
+            group(c, tb, base, zfirst, s, lds, std::make_integer_sequence<int, Q>{});
+        tail(c, tb, base, nit, zfirst, s, lds, std::make_integer_sequence<int, Q>{});
     }
 };
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST>
 __global__ __launch_bounds__(64 * NW) void stream3d_kernel(const Stream3DArgs a) {
-    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER>;
+    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST>;
     extern __shared__ __align__(16) unsigned char smem[];
     KK::run(a, reinterpret_cast<typename KK::TC*>(smem));
 }
 
-using Launcher = void (*)(const Stream3DArgs&, hipStream_t);
-
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST>
 void launch(const Stream3DArgs& a, hipStream_t s) {
-    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER>;
+    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST>;
     const int64_t tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
-    hipLaunchKernelGGL((stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER>),
-                       dim3(static_cast<unsigned>(tiles)), dim3(64 * NW), KK::LDS_BYTES, s, a);
+    hipLaunchKernelGGL((stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST>), dim3(static_cast<unsigned>(tiles)),
+                       dim3(64 * NW), KK::LDS_BYTES, s, a);
 }
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER>
-constexpr int lds_of() { return Kern<TS, R, TBMAX, VX, K, NW, PER>::LDS_BYTES; }
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST>
+constexpr int lds_of() { return Kern<TS, R, TBMAX, VX, K, NW, PER, FAST>::LDS_BYTES; }
 
 template <typename TS> constexpr int32_t dtype_of();
 template <> constexpr int32_t dtype_of<double>() { return kF64; }
 template <> constexpr int32_t dtype_of<float>() { return kF32; }
 template <> constexpr int32_t dtype_of<bf16s>() { return kBF16; }
 
-#define S3D_ENTRY(TS, R, TBM, VX, K, NW, PER)                                              \
-    Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, R, TBM, VX, K, NW},      \
-           &launch<TS, R, TBM, VX, K, NW, PER>, lds_of<TS, R, TBM, VX, K, NW, PER>()}
-#define S3D_BC(TS, R, TBM, VX, K, NW) \
-    S3D_ENTRY(TS, R, TBM, VX, K, NW, false), S3D_ENTRY(TS, R, TBM, VX, K, NW, true)
+#define S3D_ENTRY(TS, R, TBM, VX, K, NW, PER, FAST)                                            \
+    Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, R, TBM, VX, K, NW, FAST},    \
+           &launch<TS, R, TBM, VX, K, NW, PER, FAST>, lds_of<TS, R, TBM, VX, K, NW, PER, FAST>()}
+#define S3D_BC(TS, R, TBM, VX, K, NW)                                                                      \
+    S3D_ENTRY(TS, R, TBM, VX, K, NW, false, true), S3D_ENTRY(TS, R, TBM, VX, K, NW, true, true),          \
+        S3D_ENTRY(TS, R, TBM, VX, K, NW, false, false), S3D_ENTRY(TS, R, TBM, VX, K, NW, true, false)
 
 }  // namespace s3d
 }  // namespace st
