@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the stencil sweep on one MI355X.
 
-A bench "step" is one whole run of the workload: 100 fused-or-not time steps
-of the 3D 7-point heat stencil on a 512^3 FP64 grid (zero-Dirichlet ghost
-layer, alpha = 0.15, U[0,1) initial field plus one sin mode), i.e. every
-stage of the hot path (plan choice, halo-tile loads, register/DPP pattern
-mapping, fused steps, stores, pass loop) over one input.  Inputs are resident
-in HBM before the timed region starts.
+Default workload (the headline): 100 time steps of the 3D 7-point heat
+stencil on a 512^3 FP64 grid (zero-Dirichlet ghost layer, alpha = 0.15,
+U[0,1) initial field from seed 0 plus one sin mode).  A bench "step" is one
+whole run of that workload -- every stage of the hot path (plan choice,
+halo-tile loads, register/DPP pattern mapping, fused time steps, stores,
+pass loop) over one input that is resident in HBM before timing starts.
 
 Prints ONE JSON line: throughput in Gcell-updates/s (Eq. 5 of the paper:
-cells x steps / time), the dominant kernel's HBM roofline figures measured
-with HIP events on the run stream, and the CPU oracle timed on a bounded
-sample of the same workload.  Secondary figures (FP32 on the same workload,
-the batched ensemble) are reported under "secondary".
+cells x time steps / time), the dominant kernel's HBM roofline figures
+measured with HIP events on the run stream, and the CPU oracle timed on a
+bounded sample of the same workload.  Secondary figures (FP32 on the same
+workload, the batched FP32 ensemble) are reported under "secondary".
+
+Other workloads (--workload): heat2d (2D 5-point FP64 512^2, 100 steps),
+box2d (2D 9-point box FP32 8192^2, 1000 steps, periodic), star25 (3D order-4
+25-point star FP32 512^3, 50 steps, periodic), batch (64 2D 5-point grids,
+sides log-uniform in [256, 4096], 500 steps).
 """
 from __future__ import annotations
 
@@ -29,21 +34,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+BYTES = {"f64": 8, "f32": 4, "bf16": 2}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _events(torch):
-    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-
 def time_runs(torch, fn, steps, warmup):
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    e0, e1 = _events(torch)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
         fn()
@@ -52,25 +55,131 @@ def time_runs(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / 1e3  # seconds
 
 
-def heat3d_workload(torch, st, synth, dtype, n=512, steps=100, alpha=0.15, select=None):
+def passes_of(steps, tb):
+    """Launches of the fused kernel per run (the pass list is made even)."""
+    n = -(-steps // tb)
+    if n % 2 == 1 and tb > 1:
+        n += 1
+    return n
+
+
+def _tdt(torch, dtype):
+    return {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+
+
+def _select(args):
+    if args.variant >= 0:
+        return {"variant": args.variant}
+    if args.tb > 0:
+        return {"tb": args.tb}
+    return None
+
+
+class Workload:
+    """A plan, its device buffers and the figures needed for the report."""
+
+
+def heat3d(torch, st, synth, dtype, select=None, n=512, steps=100, alpha=0.15):
+    w = Workload()
     shape = (n, n, n)
-    offs = synth.star_offsets(3, 1)
     wdt = "f64" if dtype == "f64" else "f32"
-    w = list(synth.heat_weights(3, alpha, wdt))
-    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
-    # U[0,1) from seed 0 plus the closed-form mode, built on the device in
-    # slices so the host never holds more than one plane set at a time
-    u = torch.empty(shape, dtype=tdt, device="cuda")
-    mode_axis = [np.sin(np.pi * (np.arange(n) + 1.0) / (n + 1.0))] * 3
-    noise = synth.uniform_field(shape, seed=0)
-    mode = np.einsum("i,j,k->ijk", *mode_axis)
-    u.copy_(torch.from_numpy(noise + mode))
-    del noise, mode
-    work = torch.empty_like(u)
-    plan = st.Plan(offs, shape, dtype, "zero")
+    w.coeffs = list(synth.heat_weights(3, alpha, wdt))
+    mode = np.einsum("i,j,k->ijk", *([np.sin(np.pi * (np.arange(n) + 1.0) / (n + 1.0))] * 3))
+    w.u = torch.from_numpy(synth.uniform_field(shape, seed=0) + mode).to("cuda", _tdt(torch, dtype))
+    del mode
+    w.work = torch.empty_like(w.u)
+    w.plan = st.Plan(synth.star_offsets(3, 1), shape, dtype, "zero")
     if select:
-        plan.select(**select)
-    return plan, u, work, w, steps
+        w.plan.select(**select)
+    w.steps, w.cells, w.dtype = steps, n ** 3, dtype
+    w.name = f"3D 7-point heat stencil, {n}^3, {steps} steps, alpha {alpha}, zero boundary"
+    w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
+    w.kernel_tb = w.plan.info()["tb"]
+    return w
+
+
+def heat2d(torch, st, synth, dtype, select=None, n=512, steps=100, alpha=0.2):
+    w = Workload()
+    shape = (n, n)
+    w.coeffs = list(synth.heat_weights(2, alpha, "f64" if dtype == "f64" else "f32"))
+    w.u = torch.from_numpy(synth.uniform_field(shape, seed=0)).to("cuda", _tdt(torch, dtype))
+    w.work = torch.empty_like(w.u)
+    w.plan = st.Plan(synth.star_offsets(2, 1), shape, dtype, "zero")
+    if select:
+        w.plan.select(**select)
+    w.steps, w.cells, w.dtype = steps, n * n, dtype
+    w.name = f"2D 5-point heat stencil, {n}^2, {steps} steps, alpha {alpha}, zero boundary"
+    w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
+    w.kernel_tb = w.plan.info()["tb"]
+    return w
+
+
+def box2d(torch, st, synth, dtype, select=None, n=8192, steps=1000):
+    w = Workload()
+    shape = (n, n)
+    w.coeffs = list(synth.box_mean_weights(2, 1, "f64" if dtype == "f64" else "f32"))
+    w.u = torch.from_numpy(synth.uniform_field(shape, seed=0)).to("cuda", _tdt(torch, dtype))
+    w.work = torch.empty_like(w.u)
+    w.plan = st.Plan(synth.box_offsets(2, 1), shape, dtype, "periodic")
+    if select:
+        w.plan.select(**select)
+    w.steps, w.cells, w.dtype = steps, n * n, dtype
+    w.name = f"2D 9-point box stencil (weights 1/9), {n}^2, {steps} steps, periodic"
+    w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
+    w.kernel_tb = w.plan.info()["tb"]
+    return w
+
+
+def star25(torch, st, synth, dtype, select=None, n=512, steps=50):
+    w = Workload()
+    shape = (n, n, n)
+    w.coeffs = list(synth.star25_weights(0, "f64" if dtype == "f64" else "f32"))
+    w.u = torch.from_numpy(synth.uniform_field(shape, seed=0)).to("cuda", _tdt(torch, dtype))
+    w.work = torch.empty_like(w.u)
+    w.plan = st.Plan(synth.star_offsets(3, 4), shape, dtype, "periodic")
+    if select:
+        w.plan.select(**select)
+    w.steps, w.cells, w.dtype = steps, n ** 3, dtype
+    w.name = f"3D order-4 25-point star stencil, {n}^3, {steps} steps, periodic"
+    w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
+    w.kernel_tb = w.plan.info()["tb"]
+    return w
+
+
+def batch(torch, st, synth, dtype, select=None, ngrids=64, steps=500):
+    w = Workload()
+    shapes = synth.batch_shapes(ngrids, seed=0)
+    alphas = synth.batch_alphas(ngrids, seed=0)
+    wdt = "f64" if dtype == "f64" else "f32"
+    w.coeffs = [list(synth.heat_weights(2, a, wdt)) for a in alphas]
+    w.grids = [torch.from_numpy(synth.uniform_field(s, seed=g)).to("cuda", _tdt(torch, dtype))
+               for g, s in enumerate(shapes)]
+    w.works = [torch.empty_like(g) for g in w.grids]
+    w.plan = st.BatchPlan(synth.star_offsets(2, 1), shapes, dtype, "zero")
+    if select:
+        w.plan.select(**select)
+    w.steps = steps
+    w.cells = int(sum(a * b for a, b in shapes))
+    w.dtype = dtype
+    w.name = (f"{ngrids} 2D 5-point heat grids, sides log-uniform [256, 4096] (seed 0), "
+              f"alpha U[0.05, 0.24], {steps} steps, zero boundary")
+    w.run = lambda: w.plan.run(w.grids, w.works, w.coeffs, [steps] * ngrids)
+    w.kernel_tb = w.plan.info()["tb"]
+    return w
+
+
+WORKLOADS = {"heat3d": heat3d, "heat2d": heat2d, "box2d": box2d, "star25": star25, "batch": batch}
+DEFAULT_DTYPE = {"heat3d": "f64", "heat2d": "f64", "box2d": "f32", "star25": "f32", "batch": "f32"}
+KERNEL_NAMES = {0: "naive_kernel", 1: "stream2d_kernel", 2: "stream3d_kernel", 3: "varcoef3d_kernel"}
+
+
+def measure(torch, w, steps, warmup):
+    secs = time_runs(torch, w.run, steps, warmup)
+    value = w.cells * w.steps * steps / secs / 1e9
+    passes = passes_of(w.steps, w.kernel_tb)
+    launch_s = secs / (steps * passes)
+    alg = 2.0 * BYTES[w.dtype] * w.cells
+    return secs, value, passes, launch_s, alg
 
 
 def main():
@@ -78,12 +187,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--workload", default="heat3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--dtype", default=None, choices=["f64", "f32", "bf16"])
     ap.add_argument("--tb", type=int, default=0, help="force the fused depth (0 = plan default)")
     ap.add_argument("--variant", type=int, default=-1, help="force a tiling candidate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps in the CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=30, help="oracle steps in the CPU sample")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -99,90 +209,72 @@ def main():
     dev = torch.cuda.get_device_properties(0)
     log(f"device: {dev.name} ({getattr(dev, 'gcnArchName', '?')}), CUs {dev.multi_processor_count}")
 
-    n, T = 512, 100
-    select = {}
-    if args.variant >= 0:
-        select["variant"] = args.variant
-    elif args.tb > 0:
-        select["tb"] = args.tb
-    plan, u, work, w, T = heat3d_workload(torch, st, synth, args.dtype, n, T, select=select or None)
-    info = plan.info()
+    dtype = args.dtype or DEFAULT_DTYPE[args.workload]
+    w = WORKLOADS[args.workload](torch, st, synth, dtype, _select(args))
+    info = w.plan.info()
     log(f"plan: {info}")
-    cells = n ** 3
+    secs, value, passes, launch_s, alg = measure(torch, w, args.steps, args.warmup)
+    achieved = alg / launch_s / 1e9
+    log(f"{value:.1f} Gcell/s, {secs / args.steps * 1e3:.3f} ms/run, {passes} passes of "
+        f"{launch_s * 1e6:.1f} us, {achieved:.0f} GB/s algorithmic per pass")
 
-    def one():
-        plan.run(u, w, T, work=work)
-
-    secs = time_runs(torch, one, args.steps, args.warmup)
-    ms_per_step = secs / args.steps * 1e3
-    value = cells * T * args.steps / secs / 1e9
-    # passes per run (launches of the dominant kernel): depth tb, count even
-    tb = info["tb"]
-    passes = -(-T // tb)
-    if passes % 2 == 1 and tb > 1:
-        passes += 1
-    s_bytes = {"f64": 8, "f32": 4, "bf16": 2}[args.dtype]
-    alg_bytes = 2.0 * s_bytes * cells  # one read + one write of the grid per pass
-    launch_s = secs / (args.steps * passes)
-    achieved = alg_bytes / launch_s / 1e9
-    log(f"{value:.1f} Gcell/s, {ms_per_step:.3f} ms/run, {passes} passes of {launch_s*1e6:.1f} us, "
-        f"{achieved:.0f} GB/s algorithmic per pass")
-
-    kname = {0: "naive_kernel", 1: "stream2d_kernel", 2: "stream3d_kernel", 3: "varcoef"}[info["kernel"]]
     out = {
-        "metric": "Gcell-updates/s (3D 7-point heat, 512^3, 100 steps, FP64)",
+        "metric": "Gcell-updates/s & % HBM roofline",
         "value": round(value, 3),
         "unit": "Gcell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(secs / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.dtype,
-        "data": "synthetic: U[0,1) seed 0 plus one sin mode",
-        "config": {"workload": f"3D 7-point heat stencil, {n}^3, {T} steps, alpha 0.15, zero boundary",
-                   "grid": [n, n, n], "time_steps": T, "fused_depth": tb,
+        "dtype": dtype,
+        "data": "synthetic (seeded U[0,1) fields; see DESIGN.md input recipe)",
+        "config": {"workload": w.name, "cells": w.cells, "time_steps": w.steps,
+                   "fused_depth": w.kernel_tb,
                    "tile": [info["tile_x"], info["tile_y"], info["tile_z"]],
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": None, "launches_per_step": passes,
-                     "avg_launch_us": round(launch_s * 1e6, 2),
-                     "alg_bytes_per_launch": alg_bytes},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[info["kernel"]],
+                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "launches_per_step": passes, "avg_launch_us": round(launch_s * 1e6, 2),
+                     "alg_bytes_per_launch": alg},
+        "single_pass_roofline_frac": round(value / (PEAK_HBM_GBS / (2 * BYTES[dtype])), 4),
     }
-    single_pass_roofline = PEAK_HBM_GBS * 1e9 / (2 * s_bytes) / 1e9
-    out["single_pass_roofline_frac"] = round(value / single_pass_roofline, 4)
 
-    if not args.no_secondary:
+    if not args.no_secondary and args.workload == "heat3d":
         sec = {}
         try:
-            if args.dtype == "f64":
-                del u, work
-                torch.cuda.empty_cache()
-                p32, u32, w32b, wt32, _ = heat3d_workload(torch, st, synth, "f32", n, T)
-                s32 = time_runs(torch, lambda: p32.run(u32, wt32, T, work=w32b), max(3, args.steps // 2), 1)
-                sec["f32_same_workload_gcells"] = round(cells * T * max(3, args.steps // 2) / s32 / 1e9, 3)
-                sec["f32_tb"] = p32.info()["tb"]
-                del u32, w32b
-                torch.cuda.empty_cache()
+            del w.u, w.work
+            torch.cuda.empty_cache()
+            w32 = heat3d(torch, st, synth, "f32")
+            _, v32, _, _, _ = measure(torch, w32, max(3, args.steps // 2), 1)
+            sec["f32_same_workload_gcells"] = round(v32, 3)
+            sec["f32_fused_depth"] = w32.kernel_tb
+            del w32
+            torch.cuda.empty_cache()
+            wb = batch(torch, st, synth, "f32")
+            _, vb, _, _, _ = measure(torch, wb, 2, 1)
+            sec["batch64_f32_gcells"] = round(vb, 3)
+            del wb
+            torch.cuda.empty_cache()
         except Exception as e:  # secondary figures never hide the headline
             sec["error"] = repr(e)
         out["secondary"] = sec
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "heat3d":
         import oracle
-        sample_steps = args.cpu_steps
+        n = 512
         u0 = synth.uniform_field((n, n, n), seed=0)
         threads = oracle.max_threads()
         t0 = time.perf_counter()
-        oracle.heat(u0, 0.15, sample_steps, bc="zero", threads=threads)
+        oracle.heat(u0, 0.15, args.cpu_steps, bc="zero", threads=threads)
         dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(cells * sample_steps / dt / 1e9, 4), "unit": "Gcell-updates/s",
-                               "cores": threads, "kind": "oracle",
-                               "sample": f"oracle heat form, {n}^3 FP64, {sample_steps} of the {T} steps "
-                                         f"({dt:.1f} s)"}
+        out["cpu_baseline"] = {"value": round(n ** 3 * args.cpu_steps / dt / 1e9, 4),
+                               "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
+                               "sample": f"oracle heat form, {n}^3 FP64, first {args.cpu_steps} of the "
+                                         f"100 steps, {dt:.1f} s on {threads} threads"}
     print(json.dumps(out), flush=True)
 
 

@@ -53,20 +53,47 @@ template <> struct Storage<bf16s> {
     static __device__ __forceinline__ float round(float v) { return bf16_to_f32(f32_to_bf16(v)); }
 };
 
+// Grid memory is always addressed through global (address space 1)
+// pointers, so loads and stores are global_* instructions (not flat ones,
+// which would also tie up the LDS counter).
+#define ST_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ const ST_GLOBAL T* gptr(const void* p) {
+    return (const ST_GLOBAL T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ ST_GLOBAL T* gptr_mut(void* p) {
+    return (ST_GLOBAL T*)(p);
+}
+
+// Wave-uniform copies (SGPRs) of values read through a pointer.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<int32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<int32_t>(v >> 32));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+__device__ __forceinline__ double uni(double v) { return __longlong_as_double(uni(static_cast<int64_t>(__double_as_longlong(v)))); }
+__device__ __forceinline__ const void* uni(const void* p) {
+    return reinterpret_cast<const void*>(uni(reinterpret_cast<int64_t>(p)));
+}
+__device__ __forceinline__ void* uni(void* p) { return reinterpret_cast<void*>(uni(reinterpret_cast<int64_t>(p))); }
+
 // Scalar element access with the storage conversion.
 template <typename TS>
-__device__ __forceinline__ typename Storage<TS>::TC ld1(const TS* p) {
+__device__ __forceinline__ typename Storage<TS>::TC ld1(const ST_GLOBAL TS* p) {
     return Storage<TS>::widen(*p);
 }
 template <typename TS>
-__device__ __forceinline__ void st1(TS* p, typename Storage<TS>::TC v) {
+__device__ __forceinline__ void st1(ST_GLOBAL TS* p, typename Storage<TS>::TC v) {
     TS s = Storage<TS>::narrow(v);
     if constexpr (sizeof(TS) == 8) {
-        __builtin_nontemporal_store(__builtin_bit_cast(uint64_t, s), reinterpret_cast<uint64_t*>(p));
+        __builtin_nontemporal_store(__builtin_bit_cast(uint64_t, s), reinterpret_cast<ST_GLOBAL uint64_t*>(p));
     } else if constexpr (sizeof(TS) == 4) {
-        __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, s), reinterpret_cast<uint32_t*>(p));
+        __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, s), reinterpret_cast<ST_GLOBAL uint32_t*>(p));
     } else {
-        __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, s), reinterpret_cast<uint16_t*>(p));
+        __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, s), reinterpret_cast<ST_GLOBAL uint16_t*>(p));
     }
 }
 
@@ -76,21 +103,21 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename TS, int VX>
-__device__ __forceinline__ void ldv(const TS* p, typename Storage<TS>::TC (&out)[VX]) {
+__device__ __forceinline__ void ldv(const ST_GLOBAL TS* p, typename Storage<TS>::TC (&out)[VX]) {
     constexpr int kBytes = VX * static_cast<int>(sizeof(TS));
     static_assert(kBytes % 8 == 0, "vector access needs whole 8-byte units");
     TS vals[VX];
     if constexpr (kBytes % 16 == 0) {
         constexpr int kN = kBytes / 16;
         u32x4 raw[kN];
-        const u32x4* q = reinterpret_cast<const u32x4*>(p);
+        const ST_GLOBAL u32x4* q = reinterpret_cast<const ST_GLOBAL u32x4*>(p);
 #pragma unroll
         for (int c = 0; c < kN; ++c) raw[c] = q[c];
         __builtin_memcpy(vals, raw, kBytes);
     } else {
         constexpr int kN = kBytes / 8;
         u32x2 raw[kN];
-        const u32x2* q = reinterpret_cast<const u32x2*>(p);
+        const ST_GLOBAL u32x2* q = reinterpret_cast<const ST_GLOBAL u32x2*>(p);
 #pragma unroll
         for (int c = 0; c < kN; ++c) raw[c] = q[c];
         __builtin_memcpy(vals, raw, kBytes);
@@ -100,7 +127,7 @@ __device__ __forceinline__ void ldv(const TS* p, typename Storage<TS>::TC (&out)
 }
 
 template <typename TS, int VX>
-__device__ __forceinline__ void stv(TS* p, const typename Storage<TS>::TC (&in)[VX]) {
+__device__ __forceinline__ void stv(ST_GLOBAL TS* p, const typename Storage<TS>::TC (&in)[VX]) {
     constexpr int kBytes = VX * static_cast<int>(sizeof(TS));
     static_assert(kBytes % 8 == 0, "vector access needs whole 8-byte units");
     TS vals[VX];
@@ -110,14 +137,14 @@ __device__ __forceinline__ void stv(TS* p, const typename Storage<TS>::TC (&in)[
         constexpr int kN = kBytes / 16;
         u32x4 raw[kN];
         __builtin_memcpy(raw, vals, kBytes);
-        u32x4* q = reinterpret_cast<u32x4*>(p);
+        ST_GLOBAL u32x4* q = reinterpret_cast<ST_GLOBAL u32x4*>(p);
 #pragma unroll
         for (int c = 0; c < kN; ++c) __builtin_nontemporal_store(raw[c], q + c);
     } else {
         constexpr int kN = kBytes / 8;
         u32x2 raw[kN];
         __builtin_memcpy(raw, vals, kBytes);
-        u32x2* q = reinterpret_cast<u32x2*>(p);
+        ST_GLOBAL u32x2* q = reinterpret_cast<ST_GLOBAL u32x2*>(p);
 #pragma unroll
         for (int c = 0; c < kN; ++c) __builtin_nontemporal_store(raw[c], q + c);
     }

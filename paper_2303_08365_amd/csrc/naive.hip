@@ -12,8 +12,8 @@ template <typename TS>
 __global__ __launch_bounds__(256) void naive_kernel(const NaiveArgs a) {
     using S = Storage<TS>;
     using TC = typename S::TC;
-    const TS* __restrict__ src = static_cast<const TS*>(a.src);
-    TS* __restrict__ dst = static_cast<TS*>(a.dst);
+    const ST_GLOBAL TS* src = gptr<TS>(a.src);
+    ST_GLOBAL TS* dst = gptr_mut<TS>(a.dst);
     const int64_t nz = a.n[0], ny = a.n[1], nx = a.n[2];
     const int64_t cells = nz * ny * nx;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;

@@ -16,18 +16,20 @@
 // l+1 produce the row R above it, so step tb leaves the wave R*tb rows behind
 // the loads and is stored straight away.  x neighbours come from the lane's
 // own registers or, across the lane boundary, from lane +-1 by DPP; y
-// neighbours are other queue slots; nothing goes through LDS.
+// neighbours are other queue slots; nothing goes through LDS.  The R columns
+// just outside the strip (step 0 only) are fetched by lanes 0..R-1 (left) and
+// 32..32+R-1 (right) with the row and reach the DPP "old" operand of lanes 0
+// and 63 through readlane.
 //
-// Halo.  Step l is exact on columns [X0 - R + l*R, X0 + W + R - l*R); the
-// outermost R columns of step 0 (outside the register strip) are loaded by
-// lanes 0 and 63 and enter through the DPP "old" operand.  Only the strip
-// interior [X0 + hxa, X0 + W - hxa), hxa >= R*(tb-1), is stored; strips
-// overlap by 2*hxa columns.  Rows: a chunk of output rows [ys, ye) loads
-// rows ys - R*tb .. ye - 1 + R*tb.
+// Rows are prefetched 2R+1 rows ahead with unconditional loads (clamped or
+// wrapped indices); ghost cells of the zero rule become 0 through selects
+// when a row is consumed, so no branch separates a load from its use.
 //
-// Boundary.  Zero rule: cells outside the grid are forced to 0 at every
-// step (they are ghost cells); periodic rule: loads wrap and the halo cells
-// are genuine copies.
+// Halo.  Step l is exact on columns [X0 - R + l*R, X0 + W + R - l*R); only
+// the strip interior [X0 + hxa, X0 + W - hxa), hxa >= R*(tb-1), is stored.
+// Under the zero rule a strip crossing the grid edge is moved inward to touch
+// it (exact: the ghost layer is 0 at every step and lanes 0/63 receive 0).
+// Rows: a chunk of output rows [ys, ye) streams rows ys - R*tb .. ye-1+R*tb.
 #pragma once
 
 #include <utility>
@@ -43,93 +45,95 @@ template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER>
 struct Kern {
     using S = Storage<TS>;
     using TC = typename S::TC;
-    static constexpr int Q = 2 * R + 1;  // rows per queue
+    static_assert(VX >= R, "a lane must hold at least R columns");
+    static constexpr int Q = 2 * R + 1;  // rows per queue, also the prefetch depth
     static constexpr int W = 64 * VX;     // register strip width
     static constexpr int NP = (CLS == kStar) ? 4 * R + 1 : Q * Q;
 
     struct Ctx {
-        const TS* src;
-        TS* dst;
+        const ST_GLOBAL TS* src;
+        ST_GLOBAL TS* dst;
         int64_t ny, nx;
-        int64_t X0;       // first register column of the strip
-        int64_t xl;       // first column of this lane
-        int64_t ys, ye;   // output rows of the chunk
+        int64_t X0;             // first register column of the strip
+        int64_t xl;             // first column of this lane
+        int64_t xr_x;           // ring column this lane fetches
+        int64_t ys, ye, ylast;  // output rows of the chunk; last streamed row
         int64_t ofirst, olast;  // output columns [ofirst, olast)
-        bool fast;        // strip + ring inside the grid and aligned
         int lane;
         TC w[NP];
     };
 
-    // Load row y of the input (step 0) for this lane, plus the ring values
-    // held by the edge lanes.
-    static __device__ __forceinline__ void load_row(const Ctx& c, int64_t y, TC (&v)[VX],
-                                                    TC (&ext)[R]) {
-        const bool yin = (y >= 0 && y < c.ny);
-        if (!PER && !yin) {
-#pragma unroll
-            for (int e = 0; e < VX; ++e) v[e] = TC(0);
-#pragma unroll
-            for (int k = 0; k < R; ++k) ext[k] = TC(0);
-            return;
-        }
-        const int64_t yy = PER ? wrap_idx(y, c.ny) : y;
-        const TS* row = c.src + yy * c.nx;
-        if (c.fast) {
-            ldv<TS, VX>(row + c.xl, v);
+    static __device__ __forceinline__ int64_t fix(int64_t i, int64_t n) {
+        if (PER) return wrap_idx(i, n);
+        return i < 0 ? 0 : (i >= n ? n - 1 : i);
+    }
+    static __device__ __forceinline__ bool ghost(int64_t i, int64_t n) {
+        return !PER && (i < 0 || i >= n);
+    }
+
+    template <bool FAST>
+    static __device__ __forceinline__ void load_row(const Ctx& c, int64_t y, TC (&v)[VX], TC& xv) {
+        const ST_GLOBAL TS* row = c.src + fix(y < c.ylast ? y : c.ylast, c.ny) * c.nx;
+        if constexpr (FAST) {
+            ldv<TS, VX>(row + (PER ? wrap_idx(c.xl, c.nx) : c.xl), v);
         } else {
 #pragma unroll
-            for (int e = 0; e < VX; ++e) {
-                int64_t x = c.xl + e;
-                if (PER) {
-                    v[e] = ld1(row + wrap_idx(x, c.nx));
-                } else {
-                    v[e] = (x >= 0 && x < c.nx) ? ld1(row + x) : TC(0);
-                }
-            }
+            for (int e = 0; e < VX; ++e) v[e] = ld1(row + fix(c.xl + e, c.nx));
         }
+        xv = ld1(row + fix(c.xr_x, c.nx));
+    }
+
+    template <bool FAST>
+    static __device__ __forceinline__ void take_row(const Ctx& c, int64_t y, const TC (&v)[VX], TC xv,
+                                                    TC (&out)[VX], TC& xo) {
+        const bool yg = ghost(y, c.ny);
 #pragma unroll
-        for (int k = 0; k < R; ++k) ext[k] = TC(0);
-        if (c.lane == 0 || c.lane == 63) {
-            const int64_t xb = (c.lane == 0) ? c.X0 - R : c.X0 + W;
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                int64_t x = xb + k;
-                if (PER) {
-                    ext[k] = ld1(row + wrap_idx(x, c.nx));
-                } else {
-                    ext[k] = (x >= 0 && x < c.nx) ? ld1(row + x) : TC(0);
-                }
-            }
+        for (int e = 0; e < VX; ++e) {
+            const bool g = yg || (!FAST && ghost(c.xl + e, c.nx));
+            out[e] = g ? TC(0) : v[e];
+        }
+        xo = (yg || ghost(c.xr_x, c.nx)) ? TC(0) : xv;
+    }
+
+    static __device__ __forceinline__ TC lane_value(TC v, int src_lane) {
+        if constexpr (sizeof(TC) == 8) {
+            const uint64_t b = __double_as_longlong(v);
+            const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(b), src_lane);
+            const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), src_lane);
+            return __longlong_as_double((static_cast<uint64_t>(hi) << 32) | lo);
+        } else {
+            return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src_lane));
         }
     }
 
     // Neighbours across the lane boundary of one row: lft[k] is column
     // xl - R + k (from lane-1), rgt[k] is column xl + VX + k (from lane+1).
-    static __device__ __forceinline__ void side(const TC (&v)[VX], const TC (&ext)[R],
-                                                TC (&lft)[R], TC (&rgt)[R]) {
+    template <bool LEVEL0>
+    static __device__ __forceinline__ void side(const TC (&v)[VX], TC xr, TC (&lft)[R], TC (&rgt)[R]) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            lft[k] = from_lower(v[VX - R + k], ext[k]);
-            rgt[k] = from_upper(v[k], ext[k]);
+            const TC ol = LEVEL0 ? lane_value(xr, k) : TC(0);
+            const TC orr = LEVEL0 ? lane_value(xr, 32 + k) : TC(0);
+            lft[k] = from_lower(v[VX - R + k], ol);
+            rgt[k] = from_upper(v[k], orr);
         }
     }
 
     static __device__ __forceinline__ TC xval(const TC (&v)[VX], const TC (&lft)[R],
                                               const TC (&rgt)[R], int idx) {
-        // idx in [-R, VX + R): compile-time after unrolling
         return idx < 0 ? lft[R + idx] : (idx >= VX ? rgt[idx - VX] : v[idx]);
     }
 
     // One output row of step l+1 from the queue of step l.  J is the slot of
-    // the newest row; slot of the row dy away from the centre is
-    // (J - R + dy) mod Q.
-    template <int J>
-    static __device__ __forceinline__ void compute(const Ctx& c, const TC (&q)[Q][VX],
-                                                   const TC (&ext)[Q][R], TC (&out)[VX]) {
+    // the newest row; the row dy away from the centre is slot (J - R + dy) mod
+    // Q.  Canonical point order: centre, then (dy, dx) lexicographic.
+    template <int J, bool LEVEL0>
+    static __device__ __forceinline__ void compute(const Ctx& c, const TC (&q)[Q][VX], const TC (&xq)[Q],
+                                                   TC (&out)[VX]) {
         constexpr int CEN = (J - R + Q) % Q;
         if constexpr (CLS == kStar) {
             TC lft[R], rgt[R];
-            side(q[CEN], ext[CEN], lft, rgt);
+            side<LEVEL0>(q[CEN], xq[CEN], lft, rgt);
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
                 TC acc = c.w[0] * q[CEN][e];
@@ -151,7 +155,7 @@ struct Kern {
         } else {
             TC lft[Q][R], rgt[Q][R];
 #pragma unroll
-            for (int s = 0; s < Q; ++s) side(q[s], ext[s], lft[s], rgt[s]);
+            for (int s = 0; s < Q; ++s) side<LEVEL0>(q[s], xq[s], lft[s], rgt[s]);
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
                 TC acc = c.w[0] * q[CEN][e];
@@ -171,76 +175,95 @@ struct Kern {
         }
     }
 
-    // Zero rule: a row or column outside the grid is a ghost and stays 0;
-    // bfloat16 storage rounds every step's value.
+    // Zero rule: ghost rows/columns stay 0; bfloat16 storage rounds every step.
+    template <bool FAST>
     static __device__ __forceinline__ void finish(const Ctx& c, int64_t y, TC (&out)[VX]) {
-        if (!PER) {
-            if (y < 0 || y >= c.ny) {
+        const bool yg = ghost(y, c.ny);
 #pragma unroll
-                for (int e = 0; e < VX; ++e) out[e] = TC(0);
-            } else if (!c.fast) {
-#pragma unroll
-                for (int e = 0; e < VX; ++e) {
-                    const int64_t x = c.xl + e;
-                    if (x < 0 || x >= c.nx) out[e] = TC(0);
-                }
-            }
+        for (int e = 0; e < VX; ++e) {
+            const bool g = yg || (!FAST && ghost(c.xl + e, c.nx));
+            out[e] = g ? TC(0) : S::round(out[e]);
         }
-#pragma unroll
-        for (int e = 0; e < VX; ++e) out[e] = S::round(out[e]);
     }
 
+    template <bool FAST>
     static __device__ __forceinline__ void store_row(const Ctx& c, int64_t y, const TC (&out)[VX]) {
         if (y < c.ys || y >= c.ye) return;
         if (c.xl < c.ofirst || c.xl >= c.olast) return;  // lanes are wholly in or out
-        TS* row = c.dst + y * c.nx;
-        if (c.fast) {
+        ST_GLOBAL TS* row = c.dst + y * c.nx;
+        if constexpr (FAST) {
             stv<TS, VX>(row + c.xl, out);
         } else {
 #pragma unroll
-            for (int e = 0; e < VX; ++e) {
-                const int64_t x = c.xl + e;
-                if (x < c.nx) st1(row + x, out[e]);
-            }
+            for (int e = 0; e < VX; ++e)
+                if (c.xl + e < c.nx) st1(row + c.xl + e, out[e]);
         }
     }
 
-    template <int J>
-    static __device__ __forceinline__ void step(const Ctx& c, int tb, int64_t it, int64_t nit,
-                                                int64_t yfirst, TC (&pf)[Q][VX],
-                                                TC (&pfx)[Q][R], TC (&q)[TBMAX][Q][VX],
-                                                TC (&ext)[Q][R]) {
+    struct State {
+        TC q[TBMAX][Q][VX];
+        TC xq[Q];           // step-0 ring values of the queued rows
+        TC pf[Q][VX];
+        TC pfx[Q];
+    };
+
+    template <bool FAST, int J>
+    static __device__ __forceinline__ void step(const Ctx& c, int tb, int64_t it, int64_t yfirst, State& s) {
         const int64_t yin = yfirst + it;
-        // step-0 row yin arrives from the prefetch slot; refill it Q rows ahead
-#pragma unroll
-        for (int e = 0; e < VX; ++e) q[0][J][e] = pf[J][e];
-#pragma unroll
-        for (int k = 0; k < R; ++k) ext[J][k] = pfx[J][k];
-        if (it + Q < nit) load_row(c, yin + Q, pf[J], pfx[J]);
+        take_row<FAST>(c, yin, s.pf[J], s.pfx[J], s.q[0][J], s.xq[J]);
+        load_row<FAST>(c, yin + Q, s.pf[J], s.pfx[J]);
 #pragma unroll
         for (int l = 0; l < TBMAX; ++l) {
             if (l < tb) {
                 TC out[VX];
                 if (l == 0) {
-                    compute<J>(c, q[0], ext, out);
+                    compute<J, true>(c, s.q[0], s.xq, out);
                 } else {
-                    TC zext[Q][R];
-#pragma unroll
-                    for (int s = 0; s < Q; ++s)
-#pragma unroll
-                        for (int k = 0; k < R; ++k) zext[s][k] = TC(0);
-                    compute<J>(c, q[l], zext, out);
+                    compute<J, false>(c, s.q[l], s.xq, out);
                 }
                 const int64_t yc = yin - static_cast<int64_t>(l + 1) * R;
-                finish(c, yc, out);
+                finish<FAST>(c, yc, out);
                 if (l + 1 == tb) {
-                    store_row(c, yc, out);
+                    store_row<FAST>(c, yc, out);
                 } else if (l + 1 < TBMAX) {
 #pragma unroll
-                    for (int e = 0; e < VX; ++e) q[l + 1][J][e] = out[e];
+                    for (int e = 0; e < VX; ++e) s.q[l + 1][J][e] = out[e];
                 }
             }
         }
+    }
+
+    template <bool FAST, int... J>
+    static __device__ __forceinline__ void group(const Ctx& c, int tb, int64_t base, int64_t yfirst, State& s,
+                                                 std::integer_sequence<int, J...>) {
+        (step<FAST, J>(c, tb, base + J, yfirst, s), ...);
+    }
+    template <bool FAST, int... J>
+    static __device__ __forceinline__ void tail(const Ctx& c, int tb, int64_t base, int64_t nit, int64_t yfirst,
+                                                State& s, std::integer_sequence<int, J...>) {
+        ((base + J < nit ? step<FAST, J>(c, tb, base + J, yfirst, s) : void()), ...);
+    }
+
+    template <bool FAST>
+    static __device__ void body(Ctx& c, int tb) {
+        const int64_t yfirst = c.ys - static_cast<int64_t>(R) * tb;
+        const int64_t nit = (c.ye - c.ys) + 2 * static_cast<int64_t>(R) * tb;
+        c.ylast = yfirst + nit - 1;
+        State s;
+#pragma unroll
+        for (int l = 0; l < TBMAX; ++l)
+#pragma unroll
+            for (int sl = 0; sl < Q; ++sl)
+#pragma unroll
+                for (int e = 0; e < VX; ++e) s.q[l][sl][e] = TC(0);
+#pragma unroll
+        for (int sl = 0; sl < Q; ++sl) {
+            s.xq[sl] = TC(0);
+            load_row<FAST>(c, yfirst + sl, s.pf[sl], s.pfx[sl]);
+        }
+        int64_t base = 0;
+        for (; base + Q <= nit; base += Q) group<FAST>(c, tb, base, yfirst, s, std::make_integer_sequence<int, Q>{});
+        tail<FAST>(c, tb, base, nit, yfirst, s, std::make_integer_sequence<int, Q>{});
     }
 
     static __device__ void run(const Stream2DArgs& a) {
@@ -257,61 +280,38 @@ struct Kern {
             }
             gp = a.grids + lo;
         }
-        const int tb = gp->tb;
+        // the descriptor may live in global memory: pin every field to SGPRs
+        const int tb = uni(gp->tb);
+        const int64_t tiles_x = uni(static_cast<int64_t>(gp->tiles_x));
+        const int64_t out_w = uni(static_cast<int64_t>(gp->out_w));
+        const int64_t hxa = uni(static_cast<int64_t>(gp->hxa));
+        const int64_t chunk_y = uni(static_cast<int64_t>(gp->chunk_y));
+        const bool vec_ok = uni(gp->vec_ok) != 0;
         Ctx c;
-        c.src = static_cast<const TS*>(gp->src);
-        c.dst = static_cast<TS*>(gp->dst);
-        c.ny = gp->ny;
-        c.nx = gp->nx;
-        const int64_t local = item - gp->tile_begin;
-        const int64_t tx = local % gp->tiles_x, cy = local / gp->tiles_x;
-        c.X0 = tx * gp->out_w - gp->hxa;
+        c.src = gptr<TS>(uni(gp->src));
+        c.dst = gptr_mut<TS>(uni(gp->dst));
+        c.ny = uni(gp->ny);
+        c.nx = uni(gp->nx);
         c.lane = lane;
+        const int64_t local = item - uni(gp->tile_begin);
+        const int64_t tx = local % tiles_x, cy = local / tiles_x;
+        c.ofirst = tx * out_w;
+        c.olast = c.ofirst + out_w < c.nx ? c.ofirst + out_w : c.nx;
+        c.X0 = c.ofirst - hxa;
+        const bool fast = vec_ok && (PER || c.nx >= W);
+        if (!PER && fast) c.X0 = c.X0 < 0 ? 0 : (c.X0 + W > c.nx ? c.nx - W : c.X0);
         c.xl = c.X0 + static_cast<int64_t>(lane) * VX;
-        c.ys = cy * gp->chunk_y;
-        c.ye = c.ys + gp->chunk_y < c.ny ? c.ys + gp->chunk_y : c.ny;
-        c.ofirst = c.X0 + gp->hxa;
-        c.olast = c.ofirst + gp->out_w;
-        c.fast = gp->vec_ok && (c.X0 - R >= 0) && (c.X0 + W + R <= c.nx);
-#pragma unroll
-        for (int p = 0; p < NP; ++p) c.w[p] = static_cast<TC>(gp->w[p]);
-
-        const int64_t yfirst = c.ys - static_cast<int64_t>(R) * tb;
-        const int64_t nit = (c.ye - c.ys) + 2 * static_cast<int64_t>(R) * tb;
-
-        TC pf[Q][VX], pfx[Q][R], q[TBMAX][Q][VX], ext[Q][R];
-#pragma unroll
-        for (int l = 0; l < TBMAX; ++l)
-#pragma unroll
-            for (int s = 0; s < Q; ++s)
-#pragma unroll
-                for (int e = 0; e < VX; ++e) q[l][s][e] = TC(0);
-#pragma unroll
-        for (int s = 0; s < Q; ++s) {
-#pragma unroll
-            for (int k = 0; k < R; ++k) ext[s][k] = TC(0);
-            if (s < nit) {
-                load_row(c, yfirst + s, pf[s], pfx[s]);
-            } else {
-#pragma unroll
-                for (int e = 0; e < VX; ++e) pf[s][e] = TC(0);
-#pragma unroll
-                for (int k = 0; k < R; ++k) pfx[s][k] = TC(0);
-            }
+        {
+            const bool right = lane >= 32;
+            const int k = right ? lane - 32 : lane;
+            c.xr_x = right && k < R ? c.X0 + W + k : c.X0 - R + (k < R ? k : 0);
         }
-        for (int64_t base = 0; base < nit; base += Q) {
-            unroll_steps(c, tb, base, nit, yfirst, pf, pfx, q, ext,
-                         std::make_integer_sequence<int, Q>{});
-        }
-    }
-
-    template <int... J>
-    static __device__ __forceinline__ void unroll_steps(const Ctx& c, int tb, int64_t base,
-                                                        int64_t nit, int64_t yfirst,
-                                                        TC (&pf)[Q][VX], TC (&pfx)[Q][R],
-                                                        TC (&q)[TBMAX][Q][VX], TC (&ext)[Q][R],
-                                                        std::integer_sequence<int, J...>) {
-        ((base + J < nit ? step<J>(c, tb, base + J, nit, yfirst, pf, pfx, q, ext) : void()), ...);
+        c.ys = cy * chunk_y;
+        c.ye = c.ys + chunk_y < c.ny ? c.ys + chunk_y : c.ny;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) c.w[p] = static_cast<TC>(uni(gp->w[p]));
+        if (fast) body<true>(c, tb);
+        else body<false>(c, tb);
     }
 };
 

@@ -61,8 +61,8 @@ struct Kern {
     static constexpr int LDS_BYTES = TBMAX > 1 ? 2 * BUF_ELEMS * static_cast<int>(sizeof(TC)) : 0;
 
     struct Ctx {
-        const TS* src;
-        TS* dst;
+        const ST_GLOBAL TS* src;
+        ST_GLOBAL TS* dst;
         int64_t nz, ny, nx;
         int64_t X0, Y0;
         int64_t xl;            // first column of this lane
@@ -84,7 +84,7 @@ struct Kern {
     }
 
     static __device__ __forceinline__ void load_row(const Ctx& c, int64_t zz, int64_t y, TC (&v)[VX]) {
-        const TS* row = c.src + (zz * c.ny + fix(y, c.ny)) * c.nx;
+        const ST_GLOBAL TS* row = c.src + (zz * c.ny + fix(y, c.ny)) * c.nx;
         if constexpr (FAST) {
             ldv<TS, VX>(row + (PER ? wrap_idx(c.xl, c.nx) : c.xl), v);
         } else {
@@ -230,7 +230,7 @@ struct Kern {
         for (int k = 0; k < K; ++k) {
             const int64_t y = c.yw + k;
             if (y < c.oy0 || y >= c.oy1) continue;
-            TS* row = c.dst + (z * c.ny + y) * c.nx;
+            ST_GLOBAL TS* row = c.dst + (z * c.ny + y) * c.nx;
             if constexpr (FAST) {
                 stv<TS, VX>(row + c.xl, out[k]);
             } else {
@@ -326,8 +326,8 @@ struct Kern {
         const int64_t tx = item % a.tiles_x;
         const int64_t ty = (item / a.tiles_x) % a.tiles_y;
         const int64_t cz = item / (static_cast<int64_t>(a.tiles_x) * a.tiles_y);
-        c.src = static_cast<const TS*>(a.src);
-        c.dst = static_cast<TS*>(a.dst);
+        c.src = gptr<TS>(a.src);
+        c.dst = gptr_mut<TS>(a.dst);
         c.nz = a.nz;
         c.ny = a.ny;
         c.nx = a.nx;
