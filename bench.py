@@ -168,8 +168,43 @@ def batch(torch, st, synth, dtype, select=None, ngrids=64, steps=500):
     return w
 
 
-WORKLOADS = {"heat3d": heat3d, "heat2d": heat2d, "box2d": box2d, "star25": star25, "batch": batch}
-DEFAULT_DTYPE = {"heat3d": "f64", "heat2d": "f64", "box2d": "f32", "star25": "f32", "batch": "f32"}
+def varcoef(torch, st, synth, dtype, select=None, n=256, steps=200, every=20, alpha=0.1):
+    """Forward with checkpoints plus the full adjoint (dL/du0, dL/dk) of an MSE loss."""
+    w = Workload()
+    shape = (n, n, n)
+    u0, k, y = synth.varcoef_inputs(shape, seed=0)
+    tdt = _tdt(torch, dtype)
+    w.u0 = torch.from_numpy(u0).to("cuda", tdt)
+    w.k = torch.from_numpy(k).to("cuda", tdt)
+    w.y = torch.from_numpy(y).to("cuda", tdt)
+    del u0, k, y
+    w.u = torch.empty_like(w.u0)
+    w.work = torch.empty_like(w.u0)
+    w.lam = torch.empty_like(w.u0)
+    w.gk = torch.empty_like(w.u0)
+    w.ckpts = [torch.empty_like(w.u0) for _ in range(-(-steps // every))]
+    w.seg = torch.empty((every - 1,) + shape, dtype=tdt, device="cuda")
+    w.plan = st.varcoef_plan(shape, dtype)
+    w.steps, w.cells, w.dtype = steps, n ** 3, dtype
+    w.name = (f"3D variable-coefficient heat, {n}^3, {steps} steps, checkpoints every {every}, "
+              f"forward + adjoint of an MSE loss")
+
+    def run():
+        w.u.copy_(w.u0)
+        w.plan.run_ckpt(w.u, w.k, alpha, steps, w.work, every=every, ckpts=w.ckpts)
+        torch.sub(w.u, w.y, out=w.lam)
+        w.lam.mul_(2.0 / w.cells)
+        w.gk.zero_()
+        w.plan.adjoint(w.lam, steps, w.work, k=w.k, alpha=alpha, ckpts=w.ckpts, every=every,
+                       grad_k=w.gk, seg=w.seg)
+
+    w.run = run
+    w.kernel_tb = 1
+    return w
+
+
+WORKLOADS = {"varcoef": varcoef, "heat3d": heat3d, "heat2d": heat2d, "box2d": box2d, "star25": star25, "batch": batch}
+DEFAULT_DTYPE = {"varcoef": "f32", "heat3d": "f64", "heat2d": "f64", "box2d": "f32", "star25": "f32", "batch": "f32"}
 KERNEL_NAMES = {0: "naive_kernel", 1: "stream2d_kernel", 2: "stream3d_kernel", 3: "varcoef3d_kernel"}
 
 

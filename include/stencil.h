@@ -66,7 +66,8 @@ typedef enum { ST_BC_ZERO = 0, ST_BC_PERIODIC = 1 } st_boundary;
                                /* allocates and synchronises (not capturable)  */
 #define ST_PLAN_NAIVE 0x2u     /* force the one-step-per-launch kernel         */
 #define ST_PLAN_VARCOEF 0x4u   /* variable-coefficient heat operator (3D,      */
-                               /* radius-1 star, ST_BC_ZERO only)              */
+                               /* radius-1 star, ST_BC_ZERO, FP64/FP32 only);  */
+                               /* run with stencil_run_ckpt                    */
 
 typedef struct {
     int32_t ndim;             /* 1..3                                          */
@@ -179,6 +180,44 @@ st_status stencil_batch_plan(st_plan* out, const st_pattern* pattern, int32_t n,
  */
 st_status stencil_batch_run(st_plan plan, int32_t n, void* const* grids, void* const* works,
                             const double* coeffs, const int64_t* steps, void* stream);
+
+/*
+ * stencil_run_ckpt -- variable-coefficient heat run with checkpoints (plan
+ * made with ST_PLAN_VARCOEF: 3D radius-1 star, ST_BC_ZERO, FP64 or FP32).
+ * The step is not in the paper; it is the conservative form of the explicit
+ * heat step of Eq. 3 with a conductivity field:
+ *   u'[i] = u[i] + alpha * sum over the 6 faces f of kap_f (u[i+f] - u[i]),
+ *   kap_f = (k[i] + k[i+f]) / 2, and kap_f = k[i], u = 0 across the grid edge.
+ *   grid   device, in u^0, out u^steps (plan shape, plan storage type).
+ *   work   device buffer of the same size, clobbered.
+ *   k      device conductivity field, same shape and type.
+ *   ckpts  NULL, or ceil(steps/every) device buffers of the grid's size: the
+ *          call stores u^(c*every) into ckpts[c] before step c*every.
+ * Errors: ST_ERR_ARG, ST_ERR_MISMATCH (plan without ST_PLAN_VARCOEF), ST_ERR_HIP.
+ */
+st_status stencil_run_ckpt(st_plan plan, void* grid, void* work, const void* k, double alpha,
+                           int64_t steps, int64_t every, void* const* ckpts, void* stream);
+
+/*
+ * stencil_adjoint_run -- reverse-mode sweep: lambda holds dL/du^steps on
+ * entry and dL/du^0 on exit.
+ *   Constant-weight plan: k, grad_k NULL; coeffs as for stencil_run; runs
+ *     the transposed stencil (every offset negated, same boundary) `steps`
+ *     times; ckpts, every and seg are ignored.
+ *   Variable-coefficient plan: coeffs ignored; k and alpha as in the forward
+ *     run; ckpts / every as stored by stencil_run_ckpt.  Each checkpoint
+ *     segment is recomputed forward into `seg` (min(every, steps) - 1
+ *     buffers of the grid's size, laid out back to back; NULL allowed when
+ *     every == 1), then stepped back.  grad_k (NULL or a device buffer of the
+ *     grid's size) receives += dL/dk.  The step's transpose is the same step
+ *     (the operator is symmetric); the k derivative is gathered per cell, so
+ *     no atomics are used and results are deterministic.
+ *   work   device buffer of the grid's size, clobbered.
+ * Errors: ST_ERR_ARG, ST_ERR_MISMATCH, ST_ERR_HIP.
+ */
+st_status stencil_adjoint_run(st_plan plan, const void* k, double alpha, const double* coeffs,
+                              void* const* ckpts, int64_t every, int64_t steps, void* lambda,
+                              void* grad_k, void* seg, void* work, void* stream);
 
 /* Thread-local text of the last failure ("" if none). */
 const char* stencil_last_error(void);

@@ -19,7 +19,7 @@ __all__ = [
     "StencilError", "Plan", "BatchPlan", "run", "library", "library_path", "build",
     "F64", "F32", "BF16", "BC_ZERO", "BC_PERIODIC", "PLAN_AUTOTUNE", "PLAN_NAIVE",
     "PLAN_VARCOEF", "KERNEL_NAIVE", "KERNEL_STREAM2D", "KERNEL_STREAM3D", "KERNEL_VARCOEF3D",
-    "STATUS",
+    "STATUS", "StencilFn", "varcoef_plan",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -93,6 +93,9 @@ def library():
             "stencil_run": [P, P, P, p_dbl, p_i64, i64, i32, P],
             "stencil_batch_plan": [ctypes.POINTER(P), ctypes.POINTER(_Pattern), i32, p_i64, i32, i32, u32],
             "stencil_batch_run": [P, i32, ctypes.POINTER(P), ctypes.POINTER(P), p_dbl, p_i64, P],
+            "stencil_run_ckpt": [P, P, P, P, ctypes.c_double, i64, i64, ctypes.POINTER(P), P],
+            "stencil_adjoint_run": [P, P, ctypes.c_double, p_dbl, ctypes.POINTER(P), i64, i64, P, P, P,
+                                    P, P],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -147,13 +150,15 @@ def _tensor_dtype(t) -> int:
 class Plan:
     """A plan for one grid shape (``stencil_plan``)."""
 
-    def __init__(self, offsets, shape, dtype="f64", bc="zero", autotune=False, naive=False):
+    def __init__(self, offsets, shape, dtype="f64", bc="zero", autotune=False, naive=False,
+                 varcoef=False):
         lib = library()
         self.offsets = [tuple(int(v) for v in o) for o in offsets]
         self.shape = tuple(int(s) for s in shape)
         self.dtype = _DTYPES[dtype]
         self.bc = _BCS[bc]
-        flags = (PLAN_AUTOTUNE if autotune else 0) | (PLAN_NAIVE if naive else 0)
+        flags = ((PLAN_AUTOTUNE if autotune else 0) | (PLAN_NAIVE if naive else 0) |
+                 (PLAN_VARCOEF if varcoef else 0))
         pat, self._flat = _pattern(self.offsets)
         shp = (ctypes.c_int64 * len(self.shape))(*self.shape)
         h = ctypes.c_void_p()
@@ -205,6 +210,51 @@ class Plan:
                                      work.data_ptr() if work is not None else None, w, shp,
                                      int(steps), self.bc, _stream_handle(stream)))
         return grid
+
+    def _same(self, t, what):
+        if tuple(t.shape) != self.shape or not t.is_contiguous() or _tensor_dtype(t) != self.dtype:
+            raise ValueError(f"{what} must be a contiguous tensor of the plan's shape and dtype")
+
+    def run_ckpt(self, grid, k, alpha: float, steps: int, work, every: int = 0, ckpts=None,
+                 stream=None):
+        """Variable-coefficient run (``stencil_run_ckpt``) in place on `grid`.
+
+        With `every` > 0, `ckpts` holds ceil(steps/every) tensors that receive
+        u^(c*every)."""
+        self._same(grid, "grid")
+        self._same(k, "k")
+        self._same(work, "work")
+        cp = None
+        if every:
+            need = -(-int(steps) // int(every))
+            if ckpts is None or len(ckpts) < need:
+                raise ValueError(f"{need} checkpoint tensors are required")
+            for c in ckpts[:need]:
+                self._same(c, "checkpoint")
+            cp = (ctypes.c_void_p * need)(*[c.data_ptr() for c in ckpts[:need]])
+        _check(library().stencil_run_ckpt(self._h, grid.data_ptr(), work.data_ptr(), k.data_ptr(),
+                                          float(alpha), int(steps), int(every), cp,
+                                          _stream_handle(stream)))
+        return grid
+
+    def adjoint(self, lam, steps: int, work, k=None, alpha: float = 0.0, coeffs=None, ckpts=None,
+                every: int = 0, grad_k=None, seg=None, stream=None):
+        """Reverse sweep (``stencil_adjoint_run``): `lam` goes from dL/du_T to dL/du_0."""
+        self._same(lam, "lambda")
+        self._same(work, "work")
+        w = _doubles(coeffs) if coeffs is not None else None
+        cp = None
+        if ckpts is not None:
+            cp = (ctypes.c_void_p * len(ckpts))(*[c.data_ptr() for c in ckpts])
+        if grad_k is not None:
+            self._same(grad_k, "grad_k")
+        if seg is not None and (not seg.is_contiguous() or seg.dtype != lam.dtype):
+            raise ValueError("seg must be contiguous and of the plan's dtype")
+        _check(library().stencil_adjoint_run(
+            self._h, k.data_ptr() if k is not None else None, float(alpha), w, cp, int(every),
+            int(steps), lam.data_ptr(), grad_k.data_ptr() if grad_k is not None else None,
+            seg.data_ptr() if seg is not None else None, work.data_ptr(), _stream_handle(stream)))
+        return lam
 
 
 class BatchPlan:
@@ -267,3 +317,68 @@ def run(grid, coeffs, offsets, steps: int, bc="zero", plan: Optional[Plan] = Non
     if plan is None:
         plan = Plan(offsets, tuple(grid.shape), _tensor_dtype(grid), bc)
     return plan.run(grid, coeffs, steps, work=work, stream=stream)
+
+
+_VC_PLANS = {}
+
+
+def varcoef_plan(shape, dtype="f32") -> Plan:
+    """Cached variable-coefficient plan (3D radius-1 star, zero boundary)."""
+    key = (tuple(int(v) for v in shape), _DTYPES[dtype])
+    if key not in _VC_PLANS:
+        star = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
+        _VC_PLANS[key] = Plan(star, key[0], key[1], "zero", varcoef=True)
+    return _VC_PLANS[key]
+
+
+def _make_stencil_fn():
+    import torch
+
+    class _StencilFn(torch.autograd.Function):
+        """u_T = (A_k)^steps u_0 for the variable-coefficient heat step A_k.
+
+        forward(u0, k, alpha, steps, every) keeps u^(c*every) checkpoints;
+        backward recomputes each segment from its checkpoint and steps the
+        adjoint back, returning (dL/du0, dL/dk)."""
+
+        @staticmethod
+        def forward(ctx, u0, k, alpha, steps, every):
+            plan = varcoef_plan(u0.shape, _tensor_dtype(u0))
+            u0c = u0.detach().contiguous()
+            kc = k.detach().contiguous()
+            nck = max(1, -(-int(steps) // int(every)))
+            ckpts = [torch.empty_like(u0c) for _ in range(nck)]
+            out = u0c.clone()
+            work = torch.empty_like(u0c)
+            plan.run_ckpt(out, kc, alpha, steps, work, every=every, ckpts=ckpts)
+            ctx.save_for_backward(kc, *ckpts)
+            ctx.alpha, ctx.steps, ctx.every, ctx.plan = float(alpha), int(steps), int(every), plan
+            return out
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            kc, *ckpts = ctx.saved_tensors
+            lam = grad_out.detach().contiguous().clone()
+            gk = torch.zeros_like(kc)
+            work = torch.empty_like(lam)
+            nseg = min(ctx.every, ctx.steps) - 1
+            seg = torch.empty((max(nseg, 1),) + tuple(lam.shape), dtype=lam.dtype, device=lam.device)
+            ctx.plan.adjoint(lam, ctx.steps, work, k=kc, alpha=ctx.alpha, ckpts=ckpts,
+                             every=ctx.every, grad_k=gk, seg=seg)
+            return lam, gk, None, None, None
+
+    return _StencilFn
+
+
+class _LazyFn:
+    """``StencilFn.apply(u0, k, alpha, steps, every)`` (imports torch on first use)."""
+
+    _fn = None
+
+    def apply(self, *args):
+        if _LazyFn._fn is None:
+            _LazyFn._fn = _make_stencil_fn()
+        return _LazyFn._fn.apply(*args)
+
+
+StencilFn = _LazyFn()

@@ -83,7 +83,11 @@ __device__ __forceinline__ void* uni(void* p) { return reinterpret_cast<void*>(u
 // Scalar element access with the storage conversion.
 template <typename TS>
 __device__ __forceinline__ typename Storage<TS>::TC ld1(const ST_GLOBAL TS* p) {
-    return Storage<TS>::widen(*p);
+    if constexpr (sizeof(TS) == 2) {
+        return bf16_to_f32(*reinterpret_cast<const ST_GLOBAL uint16_t*>(p));
+    } else {
+        return Storage<TS>::widen(*p);
+    }
 }
 template <typename TS>
 __device__ __forceinline__ void st1(ST_GLOBAL TS* p, typename Storage<TS>::TC v) {

@@ -82,4 +82,18 @@ hipError_t launch_stream3d(const Stream3DKey& k, const Stream3DArgs& a, hipStrea
 bool stream3d_has(const Stream3DKey& k);
 int stream3d_lds_bytes(const Stream3DKey& k);
 
+// ----------------------------------------------------------------------------
+// variable-coefficient 3D heat step (zero rule) and its adjoint
+// ----------------------------------------------------------------------------
+struct VarcoefArgs {
+    const void* u;      // state the step reads (u^n)
+    const void* k;      // conductivity
+    const void* lam;    // adjoint only: dL/du^{n+1}
+    void* out;          // u^{n+1} (forward) or dL/du^n (adjoint)
+    void* grad;         // adjoint only: dL/dk accumulator (+=), may be null
+    int64_t nz, ny, nx;
+    double alpha;
+};
+hipError_t launch_varcoef(int dtype, bool adjoint, const VarcoefArgs& a, hipStream_t s);
+
 }  // namespace st

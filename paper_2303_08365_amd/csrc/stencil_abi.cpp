@@ -128,6 +128,8 @@ struct st_plan_s {
     size_t table_cap = 0;         // bytes
     hipEvent_t table_done = nullptr;
     bool table_pending = false;
+    // constant-weight adjoint: the plan of the mirrored point list
+    st_plan_s* mirror = nullptr;
 };
 
 namespace {
@@ -224,6 +226,14 @@ void build_candidates(st_plan_s* p) {
     Candidate naive;
     naive.kernel = ST_KERNEL_NAIVE;
     naive.tb = 1;
+    if (p->flags & ST_PLAN_VARCOEF) {
+        Candidate v;
+        v.kernel = ST_KERNEL_VARCOEF3D;
+        v.tb = 1;
+        p->cands.push_back(v);
+        p->sel = 0;
+        return;
+    }
     const bool force_naive = (p->flags & ST_PLAN_NAIVE) != 0;
     std::vector<Candidate> fast;
     if (!force_naive && p->ndim == 2 && p->radius == 1 && (p->cls == kStar || p->cls == kBox)) {
@@ -331,7 +341,6 @@ st_status fill_plan(st_plan_s* p, const st_pattern* pat, st_dtype storage, st_bo
     if (bc != ST_BC_ZERO && bc != ST_BC_PERIODIC) return fail(ST_ERR_ARG, "boundary %d unknown", static_cast<int>(bc));
     if (flags & ~(ST_PLAN_AUTOTUNE | ST_PLAN_NAIVE | ST_PLAN_VARCOEF))
         return fail(ST_ERR_ARG, "unknown flag bits 0x%x", flags);
-    if (flags & ST_PLAN_VARCOEF) return fail(ST_ERR_UNSUPPORTED, "variable-coefficient plans are not available");
     p->ndim = pat->ndim;
     p->dtype = storage;
     p->bc = bc;
@@ -354,6 +363,12 @@ st_status fill_plan(st_plan_s* p, const st_pattern* pat, st_dtype storage, st_bo
         p->perm[i] = pts[i][3];
     }
     classify(p);
+    if (flags & ST_PLAN_VARCOEF) {
+        if (p->ndim != 3 || p->cls != kStar || p->radius != 1)
+            return fail(ST_ERR_UNSUPPORTED, "variable-coefficient plans take the 3D radius-1 star");
+        if (bc != ST_BC_ZERO) return fail(ST_ERR_UNSUPPORTED, "variable-coefficient plans use the zero boundary");
+        if (storage == ST_BF16) return fail(ST_ERR_UNSUPPORTED, "variable-coefficient plans store FP64 or FP32");
+    }
     return ST_OK;
 }
 
@@ -514,6 +529,10 @@ void describe(const st_plan_s* p, const Candidate& c, int index, st_plan_info* i
         info->tile_z = 1;
         info->block = 256;
         info->workgroups = ceil_div(g.items, 4);
+    } else if (c.kernel == ST_KERNEL_VARCOEF3D) {
+        info->tile_x = info->tile_y = info->tile_z = 1;
+        info->block = 256;
+        info->workgroups = ceil_div(plan_cells(p), 256);
     } else if (c.kernel == ST_KERNEL_STREAM3D) {
         Geo3 g;
         geo3(c, p->n, c.tb, g);
@@ -614,6 +633,7 @@ st_status stencil_plan_destroy(st_plan plan) {
     if (plan->table_dev) hipFree(plan->table_dev);
     if (plan->table_host) hipHostFree(plan->table_host);
     if (plan->table_done) hipEventDestroy(plan->table_done);
+    if (plan->mirror) stencil_plan_destroy(plan->mirror);
     delete plan;
     return ST_OK;
 }
@@ -657,6 +677,8 @@ st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs
                       int64_t steps, st_boundary bc, void* stream) {
     if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
     if (plan->batch) return fail(ST_ERR_MISMATCH, "batch plan passed to stencil_run");
+    if (plan->flags & ST_PLAN_VARCOEF)
+        return fail(ST_ERR_MISMATCH, "variable-coefficient plan passed to stencil_run (use stencil_run_ckpt)");
     if (!shape) return fail(ST_ERR_ARG, "shape is NULL");
     for (int d = 0; d < plan->ndim; ++d)
         if (shape[d] != plan->shape[d])
@@ -858,5 +880,126 @@ extern "C" st_status stencil_batch_run(st_plan plan, int32_t n, void* const* gri
         const size_t bytes = static_cast<size_t>(plan->grids[g].ny * plan->grids[g].nx) * elem_bytes(plan->dtype);
         ST_HIP(hipMemcpyAsync(grids[g], works[g], bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(batch copy)");
     }
+    return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// variable-coefficient forward with checkpoints, and the adjoint
+// ---------------------------------------------------------------------------
+namespace {
+
+char* at(void* base, int64_t index, size_t bytes) {
+    return static_cast<char*>(base) + static_cast<size_t>(index) * bytes;
+}
+
+st_status varcoef_launch(const st_plan_s* p, bool adjoint, const void* u, const void* k, const void* lam,
+                         void* out, void* grad, double alpha, hipStream_t s) {
+    VarcoefArgs a;
+    a.u = u;
+    a.k = k;
+    a.lam = lam;
+    a.out = out;
+    a.grad = grad;
+    a.nz = p->n[0];
+    a.ny = p->n[1];
+    a.nx = p->n[2];
+    a.alpha = alpha;
+    const hipError_t e = launch_varcoef(p->dtype, adjoint, a, s);
+    if (e != hipSuccess) return hip_fail(e, adjoint ? "varcoef adjoint launch" : "varcoef step launch");
+    return ST_OK;
+}
+
+}  // namespace
+
+extern "C" st_status stencil_run_ckpt(st_plan plan, void* grid, void* work, const void* k, double alpha,
+                                      int64_t steps, int64_t every, void* const* ckpts, void* stream) {
+    if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
+    if (!(plan->flags & ST_PLAN_VARCOEF)) return fail(ST_ERR_MISMATCH, "plan was not made with ST_PLAN_VARCOEF");
+    if (steps < 0) return fail(ST_ERR_ARG, "steps = %lld < 0", static_cast<long long>(steps));
+    if (ckpts && every < 1) return fail(ST_ERR_ARG, "checkpoint interval %lld < 1", static_cast<long long>(every));
+    if (!std::isfinite(alpha)) return fail(ST_ERR_ARG, "alpha is not finite");
+    if (steps == 0) return ST_OK;
+    if (!grid || !work || !k) return fail(ST_ERR_ARG, "grid, work and k are required");
+    if (grid == work) return fail(ST_ERR_ARG, "work aliases grid");
+    if (ckpts) {
+        for (int64_t c = 0; c < ceil_div(steps, every); ++c)
+            if (!ckpts[c]) return fail(ST_ERR_ARG, "checkpoint buffer %lld is NULL", static_cast<long long>(c));
+    }
+    if (st_status r = need_device(); r != ST_OK) return r;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t bytes = static_cast<size_t>(plan_cells(plan)) * elem_bytes(plan->dtype);
+    void* cur = grid;
+    void* nxt = work;
+    for (int64_t t = 0; t < steps; ++t) {
+        if (ckpts && t % every == 0)
+            ST_HIP(hipMemcpyAsync(ckpts[t / every], cur, bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(checkpoint)");
+        if (st_status r = varcoef_launch(plan, false, cur, k, nullptr, nxt, nullptr, alpha, s); r != ST_OK) return r;
+        std::swap(cur, nxt);
+    }
+    if (cur != grid) ST_HIP(hipMemcpyAsync(grid, cur, bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(work->grid)");
+    return ST_OK;
+}
+
+extern "C" st_status stencil_adjoint_run(st_plan plan, const void* k, double alpha, const double* coeffs,
+                                         void* const* ckpts, int64_t every, int64_t steps, void* lambda,
+                                         void* grad_k, void* seg, void* work, void* stream) {
+    if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
+    if (plan->batch) return fail(ST_ERR_MISMATCH, "batch plan passed to stencil_adjoint_run");
+    if (steps < 0) return fail(ST_ERR_ARG, "steps = %lld < 0", static_cast<long long>(steps));
+    if (steps == 0) return ST_OK;
+    if (!lambda || !work) return fail(ST_ERR_ARG, "lambda and work are required");
+    if (lambda == work) return fail(ST_ERR_ARG, "work aliases lambda");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t bytes = static_cast<size_t>(plan_cells(plan)) * elem_bytes(plan->dtype);
+    if (!(plan->flags & ST_PLAN_VARCOEF)) {
+        // constant weights: the transpose of u -> sum_p w_p u(x + o_p) is the
+        // same sweep with every offset negated
+        if (k || grad_k) return fail(ST_ERR_MISMATCH, "k / grad_k given to a constant-weight plan");
+        if (!coeffs) return fail(ST_ERR_ARG, "coeffs is NULL");
+        if (!plan->mirror) {
+            std::vector<int32_t> off(static_cast<size_t>(plan->npoints) * plan->ndim);
+            for (int i = 0; i < plan->npoints; ++i) {
+                const int src = plan->perm[i];  // caller's index of canonical point i
+                for (int d = 0; d < plan->ndim; ++d)
+                    off[static_cast<size_t>(src) * plan->ndim + d] = -plan->off[i][3 - plan->ndim + d];
+            }
+            st_pattern mp{plan->ndim, plan->npoints, off.data()};
+            st_plan m = nullptr;
+            if (st_status r = stencil_plan(&m, &mp, plan->shape, static_cast<st_dtype>(plan->dtype),
+                                           static_cast<st_boundary>(plan->bc), plan->flags & ST_PLAN_NAIVE);
+                r != ST_OK)
+                return r;
+            plan->mirror = m;
+        }
+        return stencil_run(plan->mirror, lambda, work, coeffs, plan->shape, steps,
+                           static_cast<st_boundary>(plan->bc), stream);
+    }
+    if (!k) return fail(ST_ERR_ARG, "k is required for a variable-coefficient adjoint");
+    if (!ckpts || every < 1) return fail(ST_ERR_ARG, "checkpoints and an interval >= 1 are required");
+    if (!std::isfinite(alpha)) return fail(ST_ERR_ARG, "alpha is not finite");
+    const int64_t nck = ceil_div(steps, every);
+    for (int64_t c = 0; c < nck; ++c)
+        if (!ckpts[c]) return fail(ST_ERR_ARG, "checkpoint buffer %lld is NULL", static_cast<long long>(c));
+    if (std::min(every, steps) > 1 && !seg) return fail(ST_ERR_ARG, "a segment buffer of every-1 states is required");
+    if (st_status r = need_device(); r != ST_OK) return r;
+    void* cur = lambda;
+    void* nxt = work;
+    for (int64_t c = nck - 1; c >= 0; --c) {
+        const int64_t n0 = c * every;
+        const int64_t len = std::min(every, steps - n0);
+        // recompute u^{n0+1} .. u^{n0+len-1} into seg[0 .. len-2]
+        for (int64_t j = 1; j < len; ++j) {
+            const void* prev = (j == 1) ? ckpts[c] : at(seg, j - 2, bytes);
+            if (st_status r = varcoef_launch(plan, false, prev, k, nullptr, at(seg, j - 1, bytes), nullptr, alpha, s);
+                r != ST_OK)
+                return r;
+        }
+        for (int64_t j = len - 1; j >= 0; --j) {
+            const void* u = (j == 0) ? ckpts[c] : at(seg, j - 1, bytes);
+            if (st_status r = varcoef_launch(plan, true, u, k, cur, nxt, grad_k, alpha, s); r != ST_OK) return r;
+            std::swap(cur, nxt);
+        }
+    }
+    if (cur != lambda) ST_HIP(hipMemcpyAsync(lambda, cur, bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(work->lambda)");
     return ST_OK;
 }

@@ -184,3 +184,34 @@ def test_run_without_device_reports_hip_error():
     assert lib.stencil_run(h, P(FAKE), P(FAKE + 64), w, good, 3, 0, None) == -5
     assert b"hipGetDeviceCount" in lib.stencil_last_error()
     lib.stencil_plan_destroy(h)
+
+
+def test_varcoef_plan_and_validation():
+    lib = st.library()
+    p = st.varcoef_plan((16, 16, 16), "f32")
+    assert p.info()["kernel"] == st.KERNEL_VARCOEF3D
+    with pytest.raises(st.StencilError):
+        st.Plan(synth.star_offsets(3, 1), (8, 8, 8), "f32", "periodic", varcoef=True)
+    with pytest.raises(st.StencilError):
+        st.Plan(synth.box_offsets(3, 1), (8, 8, 8), "f32", varcoef=True)
+    with pytest.raises(st.StencilError):
+        st.Plan(synth.star_offsets(3, 1), (8, 8, 8), "bf16", varcoef=True)
+    P = ctypes.c_void_p
+    ck = (P * 4)(FAKE, FAKE, FAKE, None)
+    # plain plans cannot take a var-coef run, var-coef plans not a plain run
+    q = st.Plan(synth.star_offsets(3, 1), (16, 16, 16), "f32")
+    assert lib.stencil_run_ckpt(q._h, P(FAKE), P(FAKE + 64), P(FAKE), 0.1, 3, 1, None, None) == -3
+    w = (ctypes.c_double * 7)(*([0.1] * 7))
+    shp = (ctypes.c_int64 * 3)(16, 16, 16)
+    assert lib.stencil_run(p._h, P(FAKE), P(FAKE + 64), w, shp, 3, 0, None) == -3
+    assert lib.stencil_run_ckpt(p._h, P(FAKE), P(FAKE + 64), None, 0.1, 3, 1, None, None) == -1
+    assert lib.stencil_run_ckpt(p._h, P(FAKE), P(FAKE + 64), P(FAKE), 0.1, 3, 0, ck, None) == -1
+    assert lib.stencil_run_ckpt(p._h, P(FAKE), P(FAKE + 64), P(FAKE), 0.1, 7, 2, ck, None) == -1  # 4th NULL
+    assert lib.stencil_run_ckpt(p._h, P(FAKE), P(FAKE + 64), P(FAKE), 0.1, 0, 1, None, None) == 0
+    # adjoint: k required, interval >= 1, segment buffer when every > 1
+    assert lib.stencil_adjoint_run(p._h, None, 0.1, None, ck, 2, 4, P(FAKE), None, P(FAKE), P(FAKE + 64), None) == -1
+    assert lib.stencil_adjoint_run(p._h, P(FAKE), 0.1, None, ck, 0, 4, P(FAKE), None, P(FAKE), P(FAKE + 64), None) == -1
+    assert lib.stencil_adjoint_run(p._h, P(FAKE), 0.1, None, ck, 2, 4, P(FAKE), None, None, P(FAKE + 64), None) == -1
+    assert lib.stencil_adjoint_run(p._h, P(FAKE), 0.1, None, ck, 2, 0, P(FAKE), None, None, P(FAKE + 64), None) == 0
+    # constant-weight adjoint refuses k / grad_k
+    assert lib.stencil_adjoint_run(q._h, P(FAKE), 0.1, w, None, 0, 3, P(FAKE), None, None, P(FAKE + 64), None) == -3
