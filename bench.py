@@ -229,6 +229,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=30, help="oracle steps in the CPU sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain 512^3 FP64 device copy instead (bandwidth reference)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -243,6 +245,18 @@ def main():
     torch.cuda.init()
     dev = torch.cuda.get_device_properties(0)
     log(f"device: {dev.name} ({getattr(dev, 'gcnArchName', '?')}), CUs {dev.multi_processor_count}")
+
+    if args.copy_probe:
+        # plain device copy of one 512^3 FP64 grid: the achievable-bandwidth
+        # reference and the scale for the FETCH_SIZE / WRITE_SIZE counters
+        src = torch.ones((512, 512, 512), dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        secs = time_runs(torch, lambda: dst.copy_(src), args.steps, args.warmup)
+        nbytes = 2.0 * src.numel() * 8
+        print(json.dumps({"metric": "device copy GB/s", "value": round(nbytes * args.steps / secs / 1e9, 1),
+                          "unit": "GB/s", "bytes_per_launch": nbytes,
+                          "avg_launch_us": round(secs / args.steps * 1e6, 2)}), flush=True)
+        return
 
     dtype = args.dtype or DEFAULT_DTYPE[args.workload]
     w = WORKLOADS[args.workload](torch, st, synth, dtype, _select(args))
