@@ -104,7 +104,8 @@ def heat2d(torch, st, synth, dtype, select=None, n=512, steps=100, alpha=0.2):
     w.coeffs = list(synth.heat_weights(2, alpha, "f64" if dtype == "f64" else "f32"))
     w.u = torch.from_numpy(synth.uniform_field(shape, seed=0)).to("cuda", _tdt(torch, dtype))
     w.work = torch.empty_like(w.u)
-    w.plan = st.Plan(synth.star_offsets(2, 1), shape, dtype, "zero")
+    # a 2 MiB grid: the run is launch-bound, so its passes replay from a graph
+    w.plan = st.Plan(synth.star_offsets(2, 1), shape, dtype, "zero", graph=True)
     if select:
         w.plan.select(**select)
     w.steps, w.cells, w.dtype = steps, n * n, dtype
@@ -155,7 +156,10 @@ def batch(torch, st, synth, dtype, select=None, ngrids=64, steps=500):
     w.grids = [torch.from_numpy(synth.uniform_field(s, seed=g)).to("cuda", _tdt(torch, dtype))
                for g, s in enumerate(shapes)]
     w.works = [torch.empty_like(g) for g in w.grids]
-    w.plan = st.BatchPlan(synth.star_offsets(2, 1), shapes, dtype, "zero")
+    # tile and fused depth chosen by the library's autotuner on these shapes;
+    # the passes of a run replay from one captured HIP graph
+    w.plan = st.BatchPlan(synth.star_offsets(2, 1), shapes, dtype, "zero", autotune=select is None,
+                          graph=True)
     if select:
         w.plan.select(**select)
     w.steps = steps

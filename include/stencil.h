@@ -65,6 +65,9 @@ typedef enum { ST_BC_ZERO = 0, ST_BC_PERIODIC = 1 } st_boundary;
 #define ST_PLAN_AUTOTUNE 0x1u  /* time candidate tilings on the device now;    */
                                /* allocates and synchronises (not capturable)  */
 #define ST_PLAN_NAIVE 0x2u     /* force the one-step-per-launch kernel         */
+#define ST_PLAN_GRAPH 0x8u     /* capture a run's launches in a HIP graph and */
+                               /* replay it while the arguments are unchanged */
+                               /* (first call per argument set captures)      */
 #define ST_PLAN_VARCOEF 0x4u   /* variable-coefficient heat operator (3D,      */
                                /* radius-1 star, ST_BC_ZERO, FP64/FP32 only);  */
                                /* run with stencil_run_ckpt                    */
@@ -109,7 +112,13 @@ typedef struct {
  *            (ST_BF16 rounds every step's result to bfloat16, ties to even).
  *   flags    ST_PLAN_* bits.  With ST_PLAN_AUTOTUNE the call allocates two
  *            scratch grids, times every candidate on the current device and
- *            keeps the fastest; without it a fixed heuristic is used.
+ *            keeps the fastest; without it a fixed heuristic is used.  With
+ *            ST_PLAN_GRAPH, stencil_run captures its passes into a HIP graph
+ *            (on a plan-owned stream) the first time it sees a set of
+ *            arguments (grid, work, steps, weights, candidate) and afterwards
+ *            replays the graph with one hipGraphLaunch; a caller that is
+ *            itself capturing its stream gets the launches recorded into its
+ *            own graph instead.
  * Errors: ST_ERR_ARG, ST_ERR_UNSUPPORTED, ST_ERR_NOMEM, ST_ERR_HIP (autotune).
  */
 st_status stencil_plan(st_plan* out, const st_pattern* pattern, const int64_t* shape,
@@ -159,7 +168,11 @@ st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs
  * (an ensemble).  Each pass over all grids is ONE launch: work-groups take
  * (grid, tile) items from a device descriptor table (paper Sec. 5.2: the
  * work is split so that no worker becomes the slowest).  Supported patterns:
- * 2D star or box.  shapes: host, n * ndim extents.
+ * 2D radius-1 star or box.  shapes: host, n * ndim extents.  flags:
+ * ST_PLAN_AUTOTUNE times every tiling candidate on scratch grids of the
+ * batch's shapes (allocates, synchronises) and keeps the fastest;
+ * ST_PLAN_GRAPH captures the launches of a run into a HIP graph replayed while
+ * the arguments stay the same.
  * Errors: ST_ERR_ARG, ST_ERR_UNSUPPORTED, ST_ERR_NOMEM, ST_ERR_HIP.
  */
 st_status stencil_batch_plan(st_plan* out, const st_pattern* pattern, int32_t n,
@@ -173,9 +186,10 @@ st_status stencil_batch_plan(st_plan* out, const st_pattern* pattern, int32_t n,
  *                 stencil_run, required here).
  *   coeffs        host FP64, n * npoints, row g holds grid g's weights.
  *   steps         host, n step counts (each >= 0).
- * Results land in grids[g].  The plan uploads a descriptor table per call
- * through a plan-owned pinned buffer (waiting, if needed, for the previous
- * call's upload to finish reading it).
+ * Results land in grids[g].  The plan uploads a descriptor table through a
+ * plan-owned pinned buffer whenever the arguments differ from the previous
+ * call's (waiting, if needed, for the previous upload to finish reading it);
+ * repeated calls with the same arguments reuse the device table.
  * Errors: ST_ERR_ARG, ST_ERR_MISMATCH (n differs from the plan), ST_ERR_HIP.
  */
 st_status stencil_batch_run(st_plan plan, int32_t n, void* const* grids, void* const* works,

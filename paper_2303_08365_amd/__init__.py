@@ -18,7 +18,7 @@ from typing import Iterable, List, Optional, Sequence
 __all__ = [
     "StencilError", "Plan", "BatchPlan", "run", "library", "library_path", "build",
     "F64", "F32", "BF16", "BC_ZERO", "BC_PERIODIC", "PLAN_AUTOTUNE", "PLAN_NAIVE",
-    "PLAN_VARCOEF", "KERNEL_NAIVE", "KERNEL_STREAM2D", "KERNEL_STREAM3D", "KERNEL_VARCOEF3D",
+    "PLAN_VARCOEF", "PLAN_GRAPH", "KERNEL_NAIVE", "KERNEL_STREAM2D", "KERNEL_STREAM3D", "KERNEL_VARCOEF3D",
     "STATUS", "StencilFn", "varcoef_plan",
 ]
 
@@ -27,7 +27,7 @@ _LIB_PATH = os.path.join(_HERE, "libstencil.so")
 
 F64, F32, BF16 = 0, 1, 2
 BC_ZERO, BC_PERIODIC = 0, 1
-PLAN_AUTOTUNE, PLAN_NAIVE, PLAN_VARCOEF = 0x1, 0x2, 0x4
+PLAN_AUTOTUNE, PLAN_NAIVE, PLAN_VARCOEF, PLAN_GRAPH = 0x1, 0x2, 0x4, 0x8
 KERNEL_NAIVE, KERNEL_STREAM2D, KERNEL_STREAM3D, KERNEL_VARCOEF3D = 0, 1, 2, 3
 STATUS = {0: "ST_OK", -1: "ST_ERR_ARG", -2: "ST_ERR_UNSUPPORTED", -3: "ST_ERR_MISMATCH",
           -4: "ST_ERR_NOMEM", -5: "ST_ERR_HIP", -6: "ST_ERR_CAPTURE"}
@@ -151,14 +151,14 @@ class Plan:
     """A plan for one grid shape (``stencil_plan``)."""
 
     def __init__(self, offsets, shape, dtype="f64", bc="zero", autotune=False, naive=False,
-                 varcoef=False):
+                 varcoef=False, graph=False):
         lib = library()
         self.offsets = [tuple(int(v) for v in o) for o in offsets]
         self.shape = tuple(int(s) for s in shape)
         self.dtype = _DTYPES[dtype]
         self.bc = _BCS[bc]
         flags = ((PLAN_AUTOTUNE if autotune else 0) | (PLAN_NAIVE if naive else 0) |
-                 (PLAN_VARCOEF if varcoef else 0))
+                 (PLAN_VARCOEF if varcoef else 0) | (PLAN_GRAPH if graph else 0))
         pat, self._flat = _pattern(self.offsets)
         shp = (ctypes.c_int64 * len(self.shape))(*self.shape)
         h = ctypes.c_void_p()
@@ -260,7 +260,7 @@ class Plan:
 class BatchPlan:
     """A plan for a batch of 2D grids (``stencil_batch_plan``)."""
 
-    def __init__(self, offsets, shapes, dtype="f32", bc="zero"):
+    def __init__(self, offsets, shapes, dtype="f32", bc="zero", autotune=False, graph=False):
         lib = library()
         self.offsets = [tuple(int(v) for v in o) for o in offsets]
         self.shapes = [tuple(int(s) for s in sh) for sh in shapes]
@@ -270,8 +270,9 @@ class BatchPlan:
         flat = [s for sh in self.shapes for s in sh]
         shp = (ctypes.c_int64 * len(flat))(*flat)
         h = ctypes.c_void_p()
+        flags = (PLAN_AUTOTUNE if autotune else 0) | (PLAN_GRAPH if graph else 0)
         _check(lib.stencil_batch_plan(ctypes.byref(h), ctypes.byref(pat), len(self.shapes), shp,
-                                      self.dtype, self.bc, 0))
+                                      self.dtype, self.bc, flags))
         self._h = h
 
     def close(self):

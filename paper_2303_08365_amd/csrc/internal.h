@@ -59,6 +59,7 @@ struct Stream2DKey {
 };
 hipError_t launch_stream2d(const Stream2DKey& k, const Stream2DArgs& a, hipStream_t s);
 bool stream2d_has(const Stream2DKey& k);
+int stream2d_occupancy(const Stream2DKey& k);  // work-groups per CU, 0 if unknown
 
 // ----------------------------------------------------------------------------
 // 3D star: planes streamed along z, K rows per lane, LDS edge-row exchange
@@ -81,6 +82,7 @@ struct Stream3DKey {
 hipError_t launch_stream3d(const Stream3DKey& k, const Stream3DArgs& a, hipStream_t s);
 bool stream3d_has(const Stream3DKey& k);
 int stream3d_lds_bytes(const Stream3DKey& k);
+int stream3d_occupancy(const Stream3DKey& k);  // work-groups per CU, 0 if unknown
 
 // ----------------------------------------------------------------------------
 // variable-coefficient 3D heat step (zero rule) and its adjoint

@@ -10,11 +10,13 @@ namespace st {
 struct Entry2 {
     Stream2DKey key;
     void (*fn)(const Stream2DArgs&, hipStream_t);
+    int (*occ)();  // resident work-groups per CU on the current device (0 = unknown)
 };
 struct Entry3 {
     Stream3DKey key;
     void (*fn)(const Stream3DArgs&, hipStream_t);
     int lds;
+    int (*occ)();
 };
 struct Table2 {
     const Entry2* e;

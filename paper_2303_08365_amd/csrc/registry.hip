@@ -30,6 +30,16 @@ const Entry3* find3(const Stream3DKey& k) {
 
 bool stream2d_has(const Stream2DKey& k) { return find2(k) != nullptr; }
 
+int stream2d_occupancy(const Stream2DKey& k) {
+    const Entry2* e = find2(k);
+    return e ? e->occ() : 0;
+}
+
+int stream3d_occupancy(const Stream3DKey& k) {
+    const Entry3* e = find3(k);
+    return e ? e->occ() : 0;
+}
+
 hipError_t launch_stream2d(const Stream2DKey& k, const Stream2DArgs& a, hipStream_t s) {
     const Entry2* e = find2(k);
     if (!e) return hipErrorInvalidValue;

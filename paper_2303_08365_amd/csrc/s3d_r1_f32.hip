@@ -6,6 +6,7 @@ namespace s3d {
 static const Entry3 kTable[] = {
     S3D_BC(float, 1, 1, 4, 4, 4), S3D_BC(float, 1, 2, 4, 4, 4),
     S3D_BC(float, 1, 1, 4, 2, 8), S3D_BC(float, 1, 2, 4, 2, 8),
+    S3D_BC(float, 1, 2, 4, 4, 8), S3D_BC(float, 1, 4, 4, 2, 8),
 };
 }  // namespace s3d
 

@@ -6,6 +6,7 @@ namespace s3d {
 static const Entry3 kTable[] = {
     S3D_BC(double, 1, 1, 2, 4, 4), S3D_BC(double, 1, 2, 2, 4, 4),
     S3D_BC(double, 1, 1, 2, 2, 8), S3D_BC(double, 1, 2, 2, 2, 8),
+    S3D_BC(double, 1, 2, 2, 4, 8), S3D_BC(double, 1, 4, 2, 2, 8),
 };
 }  // namespace s3d
 

@@ -71,6 +71,63 @@ int device_lds_limit() {
     return limit;
 }
 
+// Compute units of the current device (256 on MI355X; assumed when no
+// device is present, so plans made on a host without a GPU match).
+int device_cus() {
+    static std::once_flag once;
+    static int cus = 256;
+    std::call_once(once, [] {
+        int count = 0, dev = 0, v = 0;
+        if (hipGetDeviceCount(&count) == hipSuccess && count > 0 && hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+    });
+    return cus;
+}
+
+bool have_device() {
+    static std::once_flag once;
+    static bool ok = false;
+    std::call_once(once, [] {
+        int count = 0;
+        ok = hipGetDeviceCount(&count) == hipSuccess && count > 0;
+    });
+    return ok;
+}
+
+// Fraction of the last dispatch round that is busy when `work` equal items
+// run on `cap` resident slots.
+double round_fill(int64_t work, int64_t cap) {
+    if (work <= 0 || cap <= 0) return 1.0;
+    const int64_t rounds = (work + cap - 1) / cap;
+    return static_cast<double>(work) / static_cast<double>(rounds * cap);
+}
+
+// Chunk length along the streamed axis (extent n): each chunk re-streams
+// `halo` extra planes/rows, and `per_chunk` work items exist per chunk.  The
+// choice maximises (busy fraction of the dispatch rounds)^(1/4) x (useful
+// fraction of the streamed planes); ties go to longer chunks.  The damped
+// fill term reflects measurement: waves of a partly filled last round run
+// faster, so an idle tail costs far less than its share of slots (on 512^3
+// FP64 two fused steps, 47-plane chunks (99 % fill, 92 % useful) beat
+// 86-plane chunks (72 % fill, 95 % useful) by 3 %).
+int64_t pick_chunk(int64_t n, int64_t per_chunk, int64_t cap, int64_t halo, int64_t min_chunk) {
+    double best = -1.0;
+    int64_t best_chunk = n;
+    for (int64_t c = 1; c <= std::min<int64_t>(n, 1024); ++c) {
+        const int64_t chunk = (n + c - 1) / c;
+        if ((n + chunk - 1) / chunk != c) continue;
+        if (chunk < min_chunk && c > 1) break;
+        const double useful = static_cast<double>(n) / static_cast<double>(n + c * halo);
+        const double score = std::pow(round_fill(per_chunk * c, cap), 0.25) * useful;
+        if (score > best + 1e-9) {
+            best = score;
+            best_chunk = chunk;
+        }
+    }
+    return best_chunk;
+}
+
 bool stream_capturing(hipStream_t s) {
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
@@ -96,6 +153,7 @@ struct Candidate {
     Stream2DKey k2{};
     Stream3DKey k3{};
     int32_t chunk = 0;  // y chunk (2D) or z chunk (3D); 0 = automatic
+    int32_t occ = 0;    // resident work-groups per CU (0 = unknown: assume 2)
 };
 
 struct BatchGrid {
@@ -130,6 +188,11 @@ struct st_plan_s {
     bool table_pending = false;
     // constant-weight adjoint: the plan of the mirrored point list
     st_plan_s* mirror = nullptr;
+    // ST_PLAN_GRAPH: the launches of the last run, captured and instantiated
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<uint64_t> graph_key;
+    std::vector<uint64_t> table_key;  // batch: arguments the device table was built for
 };
 
 namespace {
@@ -174,18 +237,19 @@ struct Geo2 {
     int64_t items;
 };
 
-bool geo2(const Candidate& c, int64_t ny, int64_t nx, int tb, Geo2& g) {
+// Resident waves of the 2D kernel (4 independent waves per work-group).
+int64_t wave_capacity2(const Candidate& c) { return static_cast<int64_t>(device_cus()) * (c.occ > 0 ? c.occ : 2) * 4; }
+
+bool geo2(const Candidate& c, int64_t ny, int64_t nx, int tb, Geo2& g, int64_t chunk_override = 0) {
     const int vx = c.k2.vx, R = c.k2.radius;
     g.hxa = static_cast<int32_t>(round_up(static_cast<int64_t>(R) * (tb - 1), vx));
     g.out_w = 64 * vx - 2 * g.hxa;
     if (g.out_w <= 0) return false;
     g.tiles_x = static_cast<int32_t>(ceil_div(nx, g.out_w));
-    int64_t chunk = c.chunk;
-    if (chunk <= 0) {
-        // about 2048 waves per pass: two per SIMD on 256 CUs
-        const int64_t want = std::max<int64_t>(1, 2048 / g.tiles_x);
-        chunk = std::max<int64_t>(std::max<int64_t>(16, 4 * R * tb), ceil_div(ny, want));
-    }
+    int64_t chunk = chunk_override > 0 ? chunk_override : c.chunk;
+    if (chunk <= 0)
+        chunk = pick_chunk(ny, g.tiles_x, wave_capacity2(c), 2 * static_cast<int64_t>(R) * tb,
+                           std::max<int64_t>(8, 2 * R * tb));
     chunk = std::min<int64_t>(chunk, ny);
     g.chunk_y = static_cast<int32_t>(chunk);
     g.chunks_y = static_cast<int32_t>(ceil_div(ny, chunk));
@@ -209,8 +273,9 @@ bool geo3(const Candidate& c, const int64_t n[3], int tb, Geo3& g) {
     int64_t chunk = c.chunk;
     const int64_t per_plane = static_cast<int64_t>(g.tiles_x) * g.tiles_y;
     if (chunk <= 0) {
-        const int64_t want = std::max<int64_t>(1, ceil_div(1024, per_plane));
-        chunk = std::max<int64_t>(std::max<int64_t>(8, 4 * R * tb), ceil_div(n[0], want));
+        const int64_t cap = static_cast<int64_t>(device_cus()) * (c.occ > 0 ? c.occ : 2);
+        chunk = pick_chunk(n[0], per_plane, cap, 2 * static_cast<int64_t>(R) * tb,
+                           std::max<int64_t>(8, 2 * R * tb));
     }
     chunk = std::min<int64_t>(chunk, n[0]);
     g.chunk_z = static_cast<int32_t>(chunk);
@@ -246,6 +311,7 @@ void build_candidates(st_plan_s* p) {
                 c.kernel = ST_KERNEL_STREAM2D;
                 c.tb = tb;
                 c.k2 = Stream2DKey{p->dtype, p->bc, p->cls, p->radius, tbmax, vx};
+                if (stream2d_has(c.k2) && have_device()) c.occ = stream2d_occupancy(c.k2);
                 Geo2 g;
                 if (stream2d_has(c.k2) && geo2(c, p->n[1], p->n[2], tb, g)) {
                     fast.push_back(c);
@@ -263,8 +329,9 @@ void build_candidates(st_plan_s* p) {
         struct V { int vx, k, nw; };
         std::vector<V> vs;
         if (p->radius == 1) {
-            if (p->dtype == kF64) vs = {{2, 4, 4}, {2, 2, 8}};
-            else if (p->dtype == kF32) vs = {{4, 4, 4}, {4, 2, 8}};
+            // first: the fastest measured on MI355X for 512^3 at depth 2
+            if (p->dtype == kF64) vs = {{2, 4, 8}, {2, 4, 4}, {2, 2, 8}};
+            else if (p->dtype == kF32) vs = {{4, 4, 8}, {4, 4, 4}, {4, 2, 8}};
             else vs = {{4, 4, 4}};
         } else {
             if (p->dtype == kF64) vs = {{4, 1, 8}};
@@ -279,6 +346,7 @@ void build_candidates(st_plan_s* p) {
                     c.kernel = ST_KERNEL_STREAM3D;
                     c.tb = tb;
                     c.k3 = Stream3DKey{p->dtype, p->bc, p->radius, tbmax, v.vx, v.k, v.nw, 1};
+                    if (stream3d_has(c.k3) && have_device()) c.occ = stream3d_occupancy(c.k3);
                     Geo3 g;
                     if (stream3d_has(c.k3) && geo3(c, p->n, tb, g)) {
                         fast.push_back(c);
@@ -292,6 +360,12 @@ void build_candidates(st_plan_s* p) {
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
             return (a.tb == want) > (b.tb == want);
         });
+    }
+    // STENCIL_CHUNK: fixed chunk length along the streamed axis (tuning)
+    if (const char* ch = std::getenv("STENCIL_CHUNK")) {
+        const int v = std::atoi(ch);
+        if (v > 0)
+            for (Candidate& c : fast) c.chunk = v;
     }
     p->cands = fast;
     p->cands.push_back(naive);
@@ -339,7 +413,7 @@ st_status fill_plan(st_plan_s* p, const st_pattern* pat, st_dtype storage, st_bo
     if (storage != ST_F64 && storage != ST_F32 && storage != ST_BF16)
         return fail(ST_ERR_ARG, "storage dtype %d unknown", static_cast<int>(storage));
     if (bc != ST_BC_ZERO && bc != ST_BC_PERIODIC) return fail(ST_ERR_ARG, "boundary %d unknown", static_cast<int>(bc));
-    if (flags & ~(ST_PLAN_AUTOTUNE | ST_PLAN_NAIVE | ST_PLAN_VARCOEF))
+    if (flags & ~(ST_PLAN_AUTOTUNE | ST_PLAN_NAIVE | ST_PLAN_VARCOEF | ST_PLAN_GRAPH))
         return fail(ST_ERR_ARG, "unknown flag bits 0x%x", flags);
     p->ndim = pat->ndim;
     p->dtype = storage;
@@ -587,6 +661,52 @@ st_status autotune(st_plan_s* p) {
     return ST_OK;
 }
 
+// Key of a run: every argument that ends up inside the launches.
+void key_push(std::vector<uint64_t>& k, const void* p) { k.push_back(reinterpret_cast<uintptr_t>(p)); }
+void key_push(std::vector<uint64_t>& k, int64_t v) { k.push_back(static_cast<uint64_t>(v)); }
+void key_push(std::vector<uint64_t>& k, double v) {
+    uint64_t b;
+    std::memcpy(&b, &v, sizeof(b));
+    k.push_back(b);
+}
+
+// With ST_PLAN_GRAPH the launches of a run are captured once on a plan-owned
+// stream, instantiated, and replayed with hipGraphLaunch on the caller's
+// stream while the arguments (key) stay the same.  A caller that is itself
+// capturing gets the plain launches recorded into its own graph.
+template <typename F>
+st_status run_graphed(st_plan_s* p, const std::vector<uint64_t>& key, hipStream_t s, F&& launches) {
+    if (!(p->flags & ST_PLAN_GRAPH) || stream_capturing(s)) return launches(s);
+    if (p->graph_exec && key == p->graph_key) {
+        ST_HIP(hipGraphLaunch(p->graph_exec, s), "hipGraphLaunch");
+        return ST_OK;
+    }
+    if (!p->cap_stream) ST_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    if (p->graph_exec) {
+        hipGraphExecDestroy(p->graph_exec);
+        p->graph_exec = nullptr;
+        p->graph_key.clear();
+    }
+    ST_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+    const st_status r = launches(p->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (r != ST_OK) {
+        if (g) hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    const hipError_t ei = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        p->graph_exec = nullptr;
+        return hip_fail(ei, "hipGraphInstantiate");
+    }
+    p->graph_key = key;
+    ST_HIP(hipGraphLaunch(p->graph_exec, s), "hipGraphLaunch");
+    return ST_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -634,6 +754,8 @@ st_status stencil_plan_destroy(st_plan plan) {
     if (plan->table_host) hipHostFree(plan->table_host);
     if (plan->table_done) hipEventDestroy(plan->table_done);
     if (plan->mirror) stencil_plan_destroy(plan->mirror);
+    if (plan->graph_exec) hipGraphExecDestroy(plan->graph_exec);
+    if (plan->cap_stream) hipStreamDestroy(plan->cap_stream);
     delete plan;
     return ST_OK;
 }
@@ -708,7 +830,16 @@ st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs
     if (work == grid) return fail(ST_ERR_ARG, "work aliases grid");
     double wcan[kMaxPoints];
     canonical_weights(plan, coeffs, wcan);
-    return run_steps(plan, plan->cands[plan->sel], grid, work, wcan, steps, s);
+    std::vector<uint64_t> key;
+    if (plan->flags & ST_PLAN_GRAPH) {
+        key_push(key, grid);
+        key_push(key, work);
+        key_push(key, steps);
+        key_push(key, static_cast<int64_t>(plan->sel));
+        for (int i = 0; i < plan->npoints; ++i) key_push(key, wcan[i]);
+    }
+    const Candidate cand = plan->cands[plan->sel];
+    return run_graphed(plan, key, s, [&](hipStream_t st) { return run_steps(plan, cand, grid, work, wcan, steps, st); });
 }
 
 }  // extern "C"
@@ -716,6 +847,10 @@ st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs
 // ---------------------------------------------------------------------------
 // batch
 // ---------------------------------------------------------------------------
+namespace {
+st_status batch_autotune(st_plan_s* p);
+}  // namespace
+
 extern "C" st_status stencil_batch_plan(st_plan* out, const st_pattern* pattern, int32_t n,
                                         const int64_t* shapes, st_dtype storage, st_boundary bc,
                                         uint32_t flags) {
@@ -732,6 +867,10 @@ extern "C" st_status stencil_batch_plan(st_plan* out, const st_pattern* pattern,
     if (st_status r = fill_plan(p, pattern, storage, bc, flags & ~ST_PLAN_AUTOTUNE); r != ST_OK) {
         delete p;
         return r;
+    }
+    if (flags & ST_PLAN_VARCOEF) {
+        delete p;
+        return fail(ST_ERR_UNSUPPORTED, "batched plans take constant weights");
     }
     if (p->radius != 1 || (p->cls != kStar && p->cls != kBox)) {
         delete p;
@@ -752,70 +891,96 @@ extern "C" st_status stencil_batch_plan(st_plan* out, const st_pattern* pattern,
     build_candidates(p);
     // batch runs need a fused family; drop the naive fallback when one exists
     if (p->cands.size() > 1) p->cands.pop_back();
+    if (flags & ST_PLAN_AUTOTUNE) {
+        if (st_status r = batch_autotune(p); r != ST_OK) {
+            stencil_plan_destroy(p);
+            return r;
+        }
+    }
     *out = p;
     return ST_OK;
 }
 
-extern "C" st_status stencil_batch_run(st_plan plan, int32_t n, void* const* grids, void* const* works,
-                                       const double* coeffs, const int64_t* steps, void* stream) {
-    if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
-    if (!plan->batch) return fail(ST_ERR_MISMATCH, "single-grid plan passed to stencil_batch_run");
-    if (n != static_cast<int32_t>(plan->grids.size()))
-        return fail(ST_ERR_MISMATCH, "batch of %d grids, plan has %zu", n, plan->grids.size());
-    if (!grids || !works || !coeffs || !steps) return fail(ST_ERR_ARG, "NULL batch array");
-    int64_t maxsteps = 0;
-    for (int g = 0; g < n; ++g) {
-        if (steps[g] < 0) return fail(ST_ERR_ARG, "steps[%d] < 0", g);
-        if (steps[g] > 0 && (!grids[g] || !works[g])) return fail(ST_ERR_ARG, "grid %d has a NULL buffer", g);
-        if (steps[g] > 0 && grids[g] == works[g]) return fail(ST_ERR_ARG, "grid %d: work aliases grid", g);
-        maxsteps = std::max(maxsteps, steps[g]);
-        for (int i = 0; i < plan->npoints; ++i)
-            if (!std::isfinite(coeffs[static_cast<int64_t>(g) * plan->npoints + i]))
-                return fail(ST_ERR_ARG, "coefficient %d of grid %d is not finite", i, g);
-    }
-    if (maxsteps == 0) return ST_OK;
-    if (st_status r = need_device(); r != ST_OK) return r;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const Candidate& c = plan->cands[plan->sel];
-    if (c.kernel == ST_KERNEL_NAIVE) {
-        // pattern without a fused family: grid by grid
-        st_plan_s one = *plan;
-        one.batch = false;
-        one.owned_work = nullptr;
-        one.table_dev = one.table_host = nullptr;
-        one.table_done = nullptr;
-        for (int g = 0; g < n; ++g) {
-            if (steps[g] == 0) continue;
-            one.n[1] = plan->grids[g].ny;
-            one.n[2] = plan->grids[g].nx;
-            double w[kMaxPoints];
-            canonical_weights(plan, coeffs + static_cast<int64_t>(g) * plan->npoints, w);
-            if (st_status r = run_steps(&one, c, grids[g], works[g], w, steps[g], s); r != ST_OK) return r;
+
+
+namespace {
+
+// Common y-chunk length for the grids of one batched pass: maximises the
+// busy fraction of the dispatch rounds over all grids' work items times the
+// useful fraction of the streamed rows.
+int64_t batch_chunk(const st_plan_s* p, const Candidate& c, int tb, const std::vector<int>& active) {
+    const int64_t cap = wave_capacity2(c);
+    const int64_t halo = 2 * static_cast<int64_t>(c.k2.radius) * tb;
+    int64_t maxny = 1;
+    for (int g : active) maxny = std::max(maxny, p->grids[g].ny);
+    double best = -1.0;
+    int64_t best_len = maxny;
+    for (double lf = std::max<int64_t>(8, halo); lf <= static_cast<double>(maxny) * 1.0001; lf *= 1.08) {
+        const int64_t len = static_cast<int64_t>(lf);
+        int64_t items = 0, rows = 0, streamed = 0;
+        for (int g : active) {
+            Geo2 geo;
+            if (!geo2(c, p->grids[g].ny, p->grids[g].nx, tb, geo, len)) return 0;
+            items += geo.items;
+            rows += geo.tiles_x * p->grids[g].ny;
+            streamed += geo.tiles_x * (p->grids[g].ny + static_cast<int64_t>(geo.chunks_y) * halo);
         }
-        return ST_OK;
+        const double score =
+            std::pow(round_fill(items, cap), 0.25) * static_cast<double>(rows) / static_cast<double>(streamed);
+        if (score > best + 1e-9) {
+            best = score;
+            best_len = len;
+        }
     }
-    // Per-grid pass lists; launch p covers every grid that still has a pass.
+    return best_len;
+}
+
+}  // namespace
+
+namespace {
+
+struct BatchLaunch {
+    size_t first;   // first descriptor of this pass in the device table
+    int count;      // descriptors (grids still running)
+    int64_t items;  // work items of the pass
+};
+
+// Build the per-pass descriptor table for the call's arguments and upload it
+// (skipped when the arguments equal those of the previous upload).
+st_status batch_prepare(st_plan_s* plan, const Candidate& c, int32_t n, void* const* grids, void* const* works,
+                        const double* coeffs, const int64_t* steps, const std::vector<uint64_t>& key,
+                        hipStream_t s, std::vector<BatchLaunch>& launches, std::vector<int>& copies) {
     std::vector<std::vector<int>> passes(n);
-    std::vector<char> needs_copy(n, 0);
     size_t npass = 0;
+    copies.clear();
     for (int g = 0; g < n; ++g) {
         bool copy = false;
         passes[g] = pass_list(steps[g], c.tb, copy);
-        needs_copy[g] = copy;
+        if (copy) copies.push_back(g);
         npass = std::max(npass, passes[g].size());
     }
-    // Descriptor tables, one block of up to n entries per launch.
     std::vector<Stream2DGrid> table;
-    std::vector<std::pair<size_t, int>> launches;  // (first entry, count)
-    std::vector<int64_t> items;
+    launches.clear();
+    std::vector<std::pair<int, int64_t>> chunk_for_tb;  // chunk length chosen per depth
     for (size_t pi = 0; pi < npass; ++pi) {
         const size_t first = table.size();
         int64_t begin = 0;
         for (int g = 0; g < n; ++g) {
             if (pi >= passes[g].size()) continue;
             const int tb = passes[g][pi];
+            int64_t len = 0;
+            for (const auto& ct : chunk_for_tb)
+                if (ct.first == tb) len = ct.second;
+            if (len == 0) {
+                std::vector<int> same;
+                for (int h = 0; h < n; ++h)
+                    if (pi < passes[h].size() && passes[h][pi] == tb) same.push_back(h);
+                len = c.chunk > 0 ? c.chunk : batch_chunk(plan, c, tb, same);
+                if (len <= 0) return fail(ST_ERR_UNSUPPORTED, "2D tiling infeasible for the batch");
+                chunk_for_tb.emplace_back(tb, len);
+            }
             Geo2 geo;
-            if (!geo2(c, plan->grids[g].ny, plan->grids[g].nx, tb, geo))
+            if (!geo2(c, plan->grids[g].ny, plan->grids[g].nx, tb, geo, len))
                 return fail(ST_ERR_UNSUPPORTED, "2D tiling infeasible for grid %d", g);
             Stream2DGrid G;
             std::memset(&G, 0, sizeof(G));
@@ -836,16 +1001,17 @@ extern "C" st_status stencil_batch_run(st_plan plan, int32_t n, void* const* gri
             begin += geo.items;
             table.push_back(G);
         }
-        launches.emplace_back(first, static_cast<int>(table.size() - first));
-        items.push_back(begin);
+        launches.push_back(BatchLaunch{first, static_cast<int>(table.size() - first), begin});
     }
+    if (key == plan->table_key) return ST_OK;  // the device already holds this table
     const size_t need = table.size() * sizeof(Stream2DGrid);
+    if (plan->table_pending) {
+        // the previous upload may still read the pinned buffer
+        ST_HIP(hipEventSynchronize(plan->table_done), "hipEventSynchronize(table)");
+        plan->table_pending = false;
+    }
     if (need > plan->table_cap) {
         if (stream_capturing(s)) return fail(ST_ERR_CAPTURE, "descriptor table growth during capture");
-        if (plan->table_pending) {
-            hipEventSynchronize(plan->table_done);
-            plan->table_pending = false;
-        }
         if (plan->table_dev) hipFree(plan->table_dev);
         if (plan->table_host) hipHostFree(plan->table_host);
         plan->table_dev = plan->table_host = nullptr;
@@ -856,32 +1022,164 @@ extern "C" st_status stencil_batch_run(st_plan plan, int32_t n, void* const* gri
         plan->table_cap = need;
         if (!plan->table_done) ST_HIP(hipEventCreateWithFlags(&plan->table_done, hipEventDisableTiming), "hipEventCreate");
     }
-    if (plan->table_pending) {
-        // the previous call's upload may still read the pinned buffer
-        ST_HIP(hipEventSynchronize(plan->table_done), "hipEventSynchronize(table)");
-        plan->table_pending = false;
-    }
     std::memcpy(plan->table_host, table.data(), need);
     ST_HIP(hipMemcpyAsync(plan->table_dev, plan->table_host, need, hipMemcpyHostToDevice, s), "hipMemcpyAsync(table)");
     ST_HIP(hipEventRecord(plan->table_done, s), "hipEventRecord(table)");
     plan->table_pending = true;
+    plan->table_key = key;
+    return ST_OK;
+}
+
+st_status batch_launches(const st_plan_s* plan, const Candidate& c, const std::vector<BatchLaunch>& launches,
+                         const std::vector<int>& copies, void* const* grids, void* const* works, hipStream_t s) {
     const Stream2DGrid* dev = static_cast<const Stream2DGrid*>(plan->table_dev);
-    for (size_t pi = 0; pi < launches.size(); ++pi) {
+    for (const BatchLaunch& L : launches) {
         Stream2DArgs a;
         std::memset(&a, 0, sizeof(a));
-        a.grids = dev + launches[pi].first;
-        a.ngrids = launches[pi].second;
-        a.items = items[pi];
-        hipError_t e = launch_stream2d(c.k2, a, s);
+        a.grids = dev + L.first;
+        a.ngrids = L.count;
+        a.items = L.items;
+        const hipError_t e = launch_stream2d(c.k2, a, s);
         if (e != hipSuccess) return hip_fail(e, "stream2d batch launch");
     }
-    for (int g = 0; g < n; ++g) {
-        if (!needs_copy[g]) continue;
+    for (int g : copies) {
         const size_t bytes = static_cast<size_t>(plan->grids[g].ny * plan->grids[g].nx) * elem_bytes(plan->dtype);
         ST_HIP(hipMemcpyAsync(grids[g], works[g], bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(batch copy)");
     }
     return ST_OK;
 }
+
+st_status batch_run_impl(st_plan_s* plan, int32_t n, void* const* grids, void* const* works, const double* coeffs,
+                         const int64_t* steps, hipStream_t s) {
+    const Candidate c = plan->cands[plan->sel];
+    if (c.kernel == ST_KERNEL_NAIVE) {
+        // pattern without a fused family: grid by grid
+        st_plan_s one;
+        one.ndim = plan->ndim;
+        one.dtype = plan->dtype;
+        one.bc = plan->bc;
+        one.npoints = plan->npoints;
+        std::memcpy(one.off, plan->off, sizeof(one.off));
+        std::memcpy(one.perm, plan->perm, sizeof(one.perm));
+        for (int g = 0; g < n; ++g) {
+            if (steps[g] == 0) continue;
+            one.n[1] = plan->grids[g].ny;
+            one.n[2] = plan->grids[g].nx;
+            double w[kMaxPoints];
+            canonical_weights(plan, coeffs + static_cast<int64_t>(g) * plan->npoints, w);
+            if (st_status r = run_steps(&one, c, grids[g], works[g], w, steps[g], s); r != ST_OK) return r;
+        }
+        return ST_OK;
+    }
+    std::vector<uint64_t> key;
+    key_push(key, static_cast<int64_t>(plan->sel));
+    for (int g = 0; g < n; ++g) {
+        key_push(key, grids[g]);
+        key_push(key, works[g]);
+        key_push(key, steps[g]);
+        for (int i = 0; i < plan->npoints; ++i) key_push(key, coeffs[static_cast<int64_t>(g) * plan->npoints + i]);
+    }
+    std::vector<BatchLaunch> launches;
+    std::vector<int> copies;
+    const bool replay = (plan->flags & ST_PLAN_GRAPH) && plan->graph_exec && key == plan->graph_key &&
+                        key == plan->table_key && !stream_capturing(s);
+    if (!replay) {
+        if (st_status r = batch_prepare(plan, c, n, grids, works, coeffs, steps, key, s, launches, copies); r != ST_OK)
+            return r;
+    }
+    return run_graphed(plan, key, s, [&](hipStream_t st) {
+        return batch_launches(plan, c, launches, copies, grids, works, st);
+    });
+}
+
+}  // namespace
+
+extern "C" st_status stencil_batch_run(st_plan plan, int32_t n, void* const* grids, void* const* works,
+                                       const double* coeffs, const int64_t* steps, void* stream) {
+    if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
+    if (!plan->batch) return fail(ST_ERR_MISMATCH, "single-grid plan passed to stencil_batch_run");
+    if (n != static_cast<int32_t>(plan->grids.size()))
+        return fail(ST_ERR_MISMATCH, "batch of %d grids, plan has %zu", n, plan->grids.size());
+    if (!grids || !works || !coeffs || !steps) return fail(ST_ERR_ARG, "NULL batch array");
+    int64_t maxsteps = 0;
+    for (int g = 0; g < n; ++g) {
+        if (steps[g] < 0) return fail(ST_ERR_ARG, "steps[%d] < 0", g);
+        if (steps[g] > 0 && (!grids[g] || !works[g])) return fail(ST_ERR_ARG, "grid %d has a NULL buffer", g);
+        if (steps[g] > 0 && grids[g] == works[g]) return fail(ST_ERR_ARG, "grid %d: work aliases grid", g);
+        maxsteps = std::max(maxsteps, steps[g]);
+        for (int i = 0; i < plan->npoints; ++i)
+            if (!std::isfinite(coeffs[static_cast<int64_t>(g) * plan->npoints + i]))
+                return fail(ST_ERR_ARG, "coefficient %d of grid %d is not finite", i, g);
+    }
+    if (maxsteps == 0) return ST_OK;
+    if (st_status r = need_device(); r != ST_OK) return r;
+    return batch_run_impl(plan, n, grids, works, coeffs, steps, static_cast<hipStream_t>(stream));
+}
+
+namespace {
+
+// ST_PLAN_AUTOTUNE for a batch: time every candidate on scratch grids of the
+// batch's shapes and keep the fastest per step.
+st_status batch_autotune(st_plan_s* p) {
+    if (st_status r = need_device(); r != ST_OK) return r;
+    if (p->cands.size() <= 1) return ST_OK;
+    const int n = static_cast<int>(p->grids.size());
+    std::vector<void*> g(n, nullptr), w(n, nullptr);
+    std::vector<double> coeffs(static_cast<size_t>(n) * p->npoints);
+    for (int gi = 0; gi < n; ++gi)
+        for (int i = 0; i < p->npoints; ++i)
+            coeffs[static_cast<size_t>(gi) * p->npoints + i] =
+                (i == 0) ? 1.0 - 0.1 * (p->npoints - 1) / p->npoints : 0.1 / p->npoints;
+    st_status res = ST_OK;
+    for (int gi = 0; gi < n && res == ST_OK; ++gi) {
+        const size_t bytes = static_cast<size_t>(p->grids[gi].ny * p->grids[gi].nx) * elem_bytes(p->dtype);
+        if (hipMalloc(&g[gi], bytes) != hipSuccess || hipMalloc(&w[gi], bytes) != hipSuccess)
+            res = fail(ST_ERR_NOMEM, "hipMalloc(batch autotune) failed");
+        else
+            hipMemset(g[gi], 0, bytes);
+    }
+    if (res == ST_OK) {
+        const uint32_t flags = p->flags;
+        p->flags &= ~ST_PLAN_GRAPH;
+        hipEvent_t e0, e1;
+        hipEventCreate(&e0);
+        hipEventCreate(&e1);
+        double best = 1e300;
+        int best_i = p->sel;
+        for (size_t i = 0; i < p->cands.size(); ++i) {
+            p->sel = static_cast<int>(i);
+            p->table_key.clear();
+            const int64_t st = std::max<int64_t>(2, 2 * p->cands[i].tb);
+            std::vector<int64_t> steps(n, st);
+            if (batch_run_impl(p, n, g.data(), w.data(), coeffs.data(), steps.data(), nullptr) != ST_OK) continue;
+            hipEventRecord(e0, nullptr);
+            st_status r = batch_run_impl(p, n, g.data(), w.data(), coeffs.data(), steps.data(), nullptr);
+            hipEventRecord(e1, nullptr);
+            hipEventSynchronize(e1);
+            if (r != ST_OK) continue;
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms / st < best) {
+                best = ms / st;
+                best_i = static_cast<int>(i);
+            }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        p->sel = best_i;
+        p->table_key.clear();
+        p->flags = flags;
+        g_last_error.clear();
+    }
+    hipDeviceSynchronize();
+    for (int gi = 0; gi < n; ++gi) {
+        if (g[gi]) hipFree(g[gi]);
+        if (w[gi]) hipFree(w[gi]);
+    }
+    return res;
+}
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // variable-coefficient forward with checkpoints, and the adjoint

@@ -327,6 +327,15 @@ void launch(const Stream2DArgs& a, hipStream_t s) {
                        dim3(256), 0, s, a);
 }
 
+template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER>
+int occ_of() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_kernel<TS, R, CLS, TBMAX, VX, PER>, 256, 0) !=
+        hipSuccess)
+        n = 0;
+    return n;
+}
+
 template <typename TS> constexpr int32_t dtype_of();
 template <> constexpr int32_t dtype_of<double>() { return kF64; }
 template <> constexpr int32_t dtype_of<float>() { return kF32; }
@@ -334,7 +343,7 @@ template <> constexpr int32_t dtype_of<bf16s>() { return kBF16; }
 
 #define S2D_ENTRY(TS, R, CLS, TBM, VX, PER)                                                    \
     Entry2{Stream2DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, CLS, R, TBM, VX},            \
-           &launch<TS, R, CLS, TBM, VX, PER>}
+           &launch<TS, R, CLS, TBM, VX, PER>, &occ_of<TS, R, CLS, TBM, VX, PER>}
 #define S2D_BC(TS, R, CLS, TBM, VX) \
     S2D_ENTRY(TS, R, CLS, TBM, VX, false), S2D_ENTRY(TS, R, CLS, TBM, VX, true)
 

@@ -410,6 +410,16 @@ void launch(const Stream3DArgs& a, hipStream_t s) {
 template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST>
 constexpr int lds_of() { return Kern<TS, R, TBMAX, VX, K, NW, PER, FAST>::LDS_BYTES; }
 
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST>
+int occ_of() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST>,
+                                                     64 * NW, lds_of<TS, R, TBMAX, VX, K, NW, PER, FAST>()) !=
+        hipSuccess)
+        n = 0;
+    return n;
+}
+
 template <typename TS> constexpr int32_t dtype_of();
 template <> constexpr int32_t dtype_of<double>() { return kF64; }
 template <> constexpr int32_t dtype_of<float>() { return kF32; }
@@ -417,7 +427,8 @@ template <> constexpr int32_t dtype_of<bf16s>() { return kBF16; }
 
 #define S3D_ENTRY(TS, R, TBM, VX, K, NW, PER, FAST)                                            \
     Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, R, TBM, VX, K, NW, FAST},    \
-           &launch<TS, R, TBM, VX, K, NW, PER, FAST>, lds_of<TS, R, TBM, VX, K, NW, PER, FAST>()}
+           &launch<TS, R, TBM, VX, K, NW, PER, FAST>, lds_of<TS, R, TBM, VX, K, NW, PER, FAST>(),      \
+           &occ_of<TS, R, TBM, VX, K, NW, PER, FAST>}
 #define S3D_BC(TS, R, TBM, VX, K, NW)                                                                      \
     S3D_ENTRY(TS, R, TBM, VX, K, NW, false, true), S3D_ENTRY(TS, R, TBM, VX, K, NW, true, true),          \
         S3D_ENTRY(TS, R, TBM, VX, K, NW, false, false), S3D_ENTRY(TS, R, TBM, VX, K, NW, true, false)
