@@ -104,8 +104,9 @@ def heat2d(torch, st, synth, dtype, select=None, n=512, steps=100, alpha=0.2):
     w.coeffs = list(synth.heat_weights(2, alpha, "f64" if dtype == "f64" else "f32"))
     w.u = torch.from_numpy(synth.uniform_field(shape, seed=0)).to("cuda", _tdt(torch, dtype))
     w.work = torch.empty_like(w.u)
-    # a 2 MiB grid: the run is launch-bound, so its passes replay from a graph
-    w.plan = st.Plan(synth.star_offsets(2, 1), shape, dtype, "zero", graph=True)
+    # a 2 MiB grid: the run is launch-bound, so its passes replay from a graph;
+    # fused depth and chunk length come from the library's autotuner
+    w.plan = st.Plan(synth.star_offsets(2, 1), shape, dtype, "zero", graph=True, autotune=select is None)
     if select:
         w.plan.select(**select)
     w.steps, w.cells, w.dtype = steps, n * n, dtype
@@ -121,7 +122,7 @@ def box2d(torch, st, synth, dtype, select=None, n=8192, steps=1000):
     w.coeffs = list(synth.box_mean_weights(2, 1, "f64" if dtype == "f64" else "f32"))
     w.u = torch.from_numpy(synth.uniform_field(shape, seed=0)).to("cuda", _tdt(torch, dtype))
     w.work = torch.empty_like(w.u)
-    w.plan = st.Plan(synth.box_offsets(2, 1), shape, dtype, "periodic")
+    w.plan = st.Plan(synth.box_offsets(2, 1), shape, dtype, "periodic", autotune=select is None)
     if select:
         w.plan.select(**select)
     w.steps, w.cells, w.dtype = steps, n * n, dtype

@@ -78,6 +78,7 @@ struct Stream3DArgs {
 struct Stream3DKey {
     int32_t dtype, bc, radius, tbmax, vx, k, nw;
     int32_t fast;  // whole-vector rows (see stream3d_impl.h)
+    int32_t late;  // one-plane prefetch issued after step 0 (fewer registers)
 };
 hipError_t launch_stream3d(const Stream3DKey& k, const Stream3DArgs& a, hipStream_t s);
 bool stream3d_has(const Stream3DKey& k);

@@ -301,56 +301,70 @@ void build_candidates(st_plan_s* p) {
     }
     const bool force_naive = (p->flags & ST_PLAN_NAIVE) != 0;
     std::vector<Candidate> fast;
+    // Chunk lengths along the streamed axis offered to the autotuner besides
+    // the model's choice (0): measured optima on MI355X range from 4 rows (a
+    // 512^2 grid, latency bound) through 48 (the 64-grid batch) and 95 (8192^2)
+    // to 64 planes (512^3).
+    const int chunks2[] = {0, 4, 8, 16, 32, 48, 64, 96, 128};
+    const int chunks3[] = {0, 32, 64, 128};
     if (!force_naive && p->ndim == 2 && p->radius == 1 && (p->cls == kStar || p->cls == kBox)) {
         const int vx = default_vx2(p->dtype);
         const int tbs[] = {1, 2, 4, 8};
-        for (int tb : tbs) {
-            for (int tbmax : {1, 4, 8}) {
-                if (tbmax < tb) continue;
-                Candidate c;
-                c.kernel = ST_KERNEL_STREAM2D;
-                c.tb = tb;
-                c.k2 = Stream2DKey{p->dtype, p->bc, p->cls, p->radius, tbmax, vx};
-                if (stream2d_has(c.k2) && have_device()) c.occ = stream2d_occupancy(c.k2);
-                Geo2 g;
-                if (stream2d_has(c.k2) && geo2(c, p->n[1], p->n[2], tb, g)) {
-                    fast.push_back(c);
-                    break;  // smallest instance that holds tb
+        for (int ch : chunks2) {
+            if (ch > p->n[1]) continue;
+            for (int tb : tbs) {
+                for (int tbmax : {1, 4, 8}) {
+                    if (tbmax < tb) continue;
+                    Candidate c;
+                    c.kernel = ST_KERNEL_STREAM2D;
+                    c.tb = tb;
+                    c.chunk = ch;
+                    c.k2 = Stream2DKey{p->dtype, p->bc, p->cls, p->radius, tbmax, vx};
+                    if (stream2d_has(c.k2) && have_device()) c.occ = stream2d_occupancy(c.k2);
+                    Geo2 g;
+                    if (stream2d_has(c.k2) && geo2(c, p->n[1], p->n[2], tb, g)) {
+                        fast.push_back(c);
+                        break;  // smallest instance that holds tb
+                    }
                 }
             }
         }
-        // heuristic default first: deeper fusion for narrower storage
+        // heuristic default first: deeper fusion for narrower storage, model chunk
         const int want = p->dtype == kF64 ? 4 : 8;
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
-            return (a.tb == want) > (b.tb == want);
+            return (a.tb == want && a.chunk == 0) > (b.tb == want && b.chunk == 0);
         });
     }
     if (!force_naive && p->ndim == 3 && p->cls == kStar && (p->radius == 1 || p->radius == 4)) {
-        struct V { int vx, k, nw; };
+        struct V { int vx, k, nw, late; };
         std::vector<V> vs;
         if (p->radius == 1) {
             // first: the fastest measured on MI355X for 512^3 at depth 2
-            if (p->dtype == kF64) vs = {{2, 4, 8}, {2, 4, 4}, {2, 2, 8}};
-            else if (p->dtype == kF32) vs = {{4, 4, 8}, {4, 4, 4}, {4, 2, 8}};
-            else vs = {{4, 4, 4}};
+            if (p->dtype == kF64) vs = {{2, 4, 8, 0}, {2, 4, 4, 0}, {2, 2, 8, 0}, {2, 4, 8, 1}, {2, 3, 8, 1}};
+            else if (p->dtype == kF32) vs = {{4, 4, 8, 0}, {4, 4, 4, 0}, {4, 2, 8, 0}, {4, 4, 8, 1}, {4, 3, 8, 1}};
+            else vs = {{4, 4, 4, 0}};
         } else {
-            if (p->dtype == kF64) vs = {{4, 1, 8}};
-            else if (p->dtype == kF32) vs = {{4, 2, 8}, {4, 1, 16}};
-            else vs = {{4, 2, 8}};
+            if (p->dtype == kF64) vs = {{4, 1, 8, 0}};
+            else if (p->dtype == kF32) vs = {{4, 2, 8, 0}, {4, 1, 16, 0}};
+            else vs = {{4, 2, 8, 0}};
         }
-        for (int tb = 1; tb <= 4; ++tb) {
-            for (const V& v : vs) {
-                for (int tbmax : {1, 2, 4}) {
-                    if (tbmax < tb) continue;
-                    Candidate c;
-                    c.kernel = ST_KERNEL_STREAM3D;
-                    c.tb = tb;
-                    c.k3 = Stream3DKey{p->dtype, p->bc, p->radius, tbmax, v.vx, v.k, v.nw, 1};
-                    if (stream3d_has(c.k3) && have_device()) c.occ = stream3d_occupancy(c.k3);
-                    Geo3 g;
-                    if (stream3d_has(c.k3) && geo3(c, p->n, tb, g)) {
-                        fast.push_back(c);
-                        break;
+        for (int ch : chunks3) {
+            if (ch > p->n[0]) continue;
+            for (int tb = 1; tb <= 4; ++tb) {
+                for (const V& v : vs) {
+                    for (int tbmax : {1, 2, 3, 4}) {
+                        if (tbmax < tb) continue;
+                        Candidate c;
+                        c.kernel = ST_KERNEL_STREAM3D;
+                        c.tb = tb;
+                        c.chunk = ch;
+                        c.k3 = Stream3DKey{p->dtype, p->bc, p->radius, tbmax, v.vx, v.k, v.nw, 1, v.late};
+                        if (stream3d_has(c.k3) && have_device()) c.occ = stream3d_occupancy(c.k3);
+                        Geo3 g;
+                        if (stream3d_has(c.k3) && geo3(c, p->n, tb, g)) {
+                            fast.push_back(c);
+                            break;
+                        }
                     }
                 }
             }
@@ -358,7 +372,7 @@ void build_candidates(st_plan_s* p) {
         // measured on MI355X (512^3): two fused steps beat one for radius 1
         const int want = p->radius == 1 ? 2 : 1;
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
-            return (a.tb == want) > (b.tb == want);
+            return (a.tb == want && a.chunk == 0) > (b.tb == want && b.chunk == 0);
         });
     }
     // STENCIL_CHUNK: fixed chunk length along the streamed axis (tuning)

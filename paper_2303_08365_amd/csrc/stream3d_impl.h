@@ -44,15 +44,18 @@ namespace st {
 
 namespace s3d {
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE>
 struct Kern {
     using S = Storage<TS>;
     using TC = typename S::TC;
     static_assert(VX >= R, "a lane must hold at least R columns");
     static_assert(K * R <= 32, "the x ring of a wave must fit in half a wave");
     static constexpr int Q = 2 * R + 1;
-    static constexpr int P = (Q % 3 == 0) ? 3 : Q;       // main-plane prefetch depth
-    static constexpr int PR = (R == 1) ? P : 1;          // ring prefetch depth
+    // Prefetch: P planes ahead into their own registers, or (LATE) one plane
+    // ahead straight into the step-0 queue slot that step 0 has just
+    // released, issued after step 0 so the deeper steps hide its latency.
+    static constexpr int P = LATE ? 1 : ((Q % 3 == 0) ? 3 : Q);
+    static constexpr int PR = (R == 1 && !LATE) ? P : 1;  // ring prefetch depth
     static constexpr int W = 64 * VX;
     static constexpr int H = NW * K;
     static constexpr int NP = 6 * R + 1;
@@ -243,7 +246,7 @@ struct Kern {
 
     struct State {
         TC q[TBMAX][Q][K][VX];
-        TC pf[P][K][VX];
+        TC pf[LATE ? 1 : P][K][VX];  // unused when LATE
         TC rpf[PR][2 * R][VX];
         TC xpf[PR];
     };
@@ -254,11 +257,16 @@ struct Kern {
         constexpr int SM = J % P, SR = J % PR;
         const int64_t zin = zfirst + it;
         // consume this iteration's slots, then refill them P (PR) planes ahead
-        take_main(c, zin, s.pf[SM], s.q[0][J]);
         TC above0[R][VX], below0[R][VX], xg;
-        take_ring(c, zin - R, s.rpf[SR], s.xpf[SR], above0, below0, xg);
-        load_main(c, zin + P, s.pf[SM]);
-        load_ring(c, zin + PR - R, s.rpf[SR], s.xpf[SR]);
+        if constexpr (LATE) {
+            take_main(c, zin, s.q[0][J], s.q[0][J]);
+            take_ring(c, zin - R, s.rpf[0], s.xpf[0], above0, below0, xg);
+        } else {
+            take_main(c, zin, s.pf[SM], s.q[0][J]);
+            take_ring(c, zin - R, s.rpf[SR], s.xpf[SR], above0, below0, xg);
+            load_main(c, zin + P, s.pf[SM]);
+            load_ring(c, zin + PR - R, s.rpf[SR], s.xpf[SR]);
+        }
 
         constexpr int CEN = (J - R + Q) % Q;
 #pragma unroll
@@ -267,6 +275,11 @@ struct Kern {
                 TC out[K][VX];
                 if (l == 0) {
                     compute<J, true>(c, s.q[0], xg, above0, below0, out);
+                    if constexpr (LATE) {
+                        // step 0 no longer needs its oldest plane: load the next one there
+                        load_main(c, zin + 1, s.q[0][(J + 1) % Q]);
+                        load_ring(c, zin + 1 - R, s.rpf[0], s.xpf[0]);
+                    }
                 } else {
                     TC* buf = lds + ((it * (tb - 1) + (l - 1)) & 1) * BUF_ELEMS;
 #pragma unroll
@@ -380,10 +393,15 @@ struct Kern {
                 for (int k = 0; k < K; ++k)
 #pragma unroll
                     for (int e = 0; e < VX; ++e) s.q[l][sl][k][e] = TC(0);
+        if constexpr (LATE) {
+            load_main(c, zfirst, s.q[0][0]);
+            load_ring(c, zfirst - R, s.rpf[0], s.xpf[0]);
+        } else {
 #pragma unroll
-        for (int sp = 0; sp < P; ++sp) load_main(c, zfirst + sp, s.pf[sp]);
+            for (int sp = 0; sp < P; ++sp) load_main(c, zfirst + sp, s.pf[sp]);
 #pragma unroll
-        for (int sp = 0; sp < PR; ++sp) load_ring(c, zfirst + sp - R, s.rpf[sp], s.xpf[sp]);
+            for (int sp = 0; sp < PR; ++sp) load_ring(c, zfirst + sp - R, s.rpf[sp], s.xpf[sp]);
+        }
 
         int64_t base = 0;
         for (; base + Q <= nit; base += Q)
@@ -392,30 +410,30 @@ struct Kern {
     }
 };
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE>
 __global__ __launch_bounds__(64 * NW) void stream3d_kernel(const Stream3DArgs a) {
-    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST>;
+    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE>;
     extern __shared__ __align__(16) unsigned char smem[];
     KK::run(a, reinterpret_cast<typename KK::TC*>(smem));
 }
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE>
 void launch(const Stream3DArgs& a, hipStream_t s) {
-    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST>;
+    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE>;
     const int64_t tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
-    hipLaunchKernelGGL((stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST>), dim3(static_cast<unsigned>(tiles)),
-                       dim3(64 * NW), KK::LDS_BYTES, s, a);
+    hipLaunchKernelGGL((stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE>),
+                       dim3(static_cast<unsigned>(tiles)), dim3(64 * NW), KK::LDS_BYTES, s, a);
 }
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST>
-constexpr int lds_of() { return Kern<TS, R, TBMAX, VX, K, NW, PER, FAST>::LDS_BYTES; }
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE>
+constexpr int lds_of() { return Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE>::LDS_BYTES; }
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE>
 int occ_of() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST>,
-                                                     64 * NW, lds_of<TS, R, TBMAX, VX, K, NW, PER, FAST>()) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE>,
+                                                     64 * NW,
+                                                     lds_of<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE>()) != hipSuccess)
         n = 0;
     return n;
 }
@@ -425,13 +443,14 @@ template <> constexpr int32_t dtype_of<double>() { return kF64; }
 template <> constexpr int32_t dtype_of<float>() { return kF32; }
 template <> constexpr int32_t dtype_of<bf16s>() { return kBF16; }
 
-#define S3D_ENTRY(TS, R, TBM, VX, K, NW, PER, FAST)                                            \
-    Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, R, TBM, VX, K, NW, FAST},    \
-           &launch<TS, R, TBM, VX, K, NW, PER, FAST>, lds_of<TS, R, TBM, VX, K, NW, PER, FAST>(),      \
-           &occ_of<TS, R, TBM, VX, K, NW, PER, FAST>}
-#define S3D_BC(TS, R, TBM, VX, K, NW)                                                                      \
-    S3D_ENTRY(TS, R, TBM, VX, K, NW, false, true), S3D_ENTRY(TS, R, TBM, VX, K, NW, true, true),          \
-        S3D_ENTRY(TS, R, TBM, VX, K, NW, false, false), S3D_ENTRY(TS, R, TBM, VX, K, NW, true, false)
+#define S3D_ENTRY(TS, R, TBM, VX, K, NW, PER, FAST, LATE)                                              \
+    Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, R, TBM, VX, K, NW, FAST, LATE},      \
+           &launch<TS, R, TBM, VX, K, NW, PER, FAST, LATE>, lds_of<TS, R, TBM, VX, K, NW, PER, FAST, LATE>(), \
+           &occ_of<TS, R, TBM, VX, K, NW, PER, FAST, LATE>}
+#define S3D_BCL(TS, R, TBM, VX, K, NW, LATE)                                                                \
+    S3D_ENTRY(TS, R, TBM, VX, K, NW, false, true, LATE), S3D_ENTRY(TS, R, TBM, VX, K, NW, true, true, LATE), \
+        S3D_ENTRY(TS, R, TBM, VX, K, NW, false, false, LATE), S3D_ENTRY(TS, R, TBM, VX, K, NW, true, false, LATE)
+#define S3D_BC(TS, R, TBM, VX, K, NW) S3D_BCL(TS, R, TBM, VX, K, NW, false)
 
 }  // namespace s3d
 }  // namespace st
