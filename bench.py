@@ -34,6 +34,75 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def source_hash() -> str:
+    """SHA-256 over the HIP/C++ sources of the library (names and bytes)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2303_08365_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*"))):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_lookup(key):
+    """Counter-measured HBM bytes per launch for this plan, or None when none
+    were taken or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != source_hash():
+        return None
+    for e in t.get("entries", []):
+        if e.get("key") == key:
+            return e
+    return None
+
+
+def _counter_means(path, counter):
+    """Mean of `counter` per dispatch, per kernel name, from a rocprofv3 CSV."""
+    import csv
+    out = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in out.items()}
+
+
+def ingest_counters(directory, key, out_path):
+    """Turn two rocprofv3 --pmc passes per kernel (FETCH_SIZE, WRITE_SIZE, in
+    KiB per dispatch) into bytes per launch, scaled by what the same counters
+    read for the streaming copy of a known size (one 512^3 FP64 grid)."""
+    copy_bytes = 512 ** 3 * 8
+    res = {}
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        st_m = _counter_means(os.path.join(directory, f"stencil_{counter}", "run_counter_collection.csv"), counter)
+        cp_m = _counter_means(os.path.join(directory, f"copy_{counter}", "run_counter_collection.csv"), counter)
+        cp = [v for k, v in cp_m.items() if "copy_kernel" in k]
+        sk = [(k, v) for k, v in st_m.items() if "st::" in k]
+        if not cp or not sk:
+            raise SystemExit(f"no counter rows for {counter} in {directory}")
+        sk.sort(key=lambda kv: -kv[1])
+        res[counter] = {"kernel": sk[0][0], "kib_per_dispatch": sk[0][1], "copy_kib_per_dispatch": cp[0],
+                        "scale": copy_bytes / 1024.0 / cp[0]}
+    fetch = res["FETCH_SIZE"]["kib_per_dispatch"] * res["FETCH_SIZE"]["scale"] * 1024.0
+    write = res["WRITE_SIZE"]["kib_per_dispatch"] * res["WRITE_SIZE"]["scale"] * 1024.0
+    entry = {"key": key, "kernel": res["FETCH_SIZE"]["kernel"], "fetch_bytes": fetch, "write_bytes": write,
+             "traffic_bytes": fetch + write, "counters": res}
+    doc = {"sources_sha256": source_hash(), "entries": [entry]}
+    with open(out_path, "w") as f:
+        json.dump(doc, f, indent=1)
+    print(json.dumps(entry), flush=True)
 BYTES = {"f64": 8, "f32": 4, "bf16": 2}
 
 
@@ -236,6 +305,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30, help="oracle steps in the CPU sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 512^3 FP64 device copy instead (bandwidth reference)")
+    ap.add_argument("--ingest-counters", default=None, metavar="DIR",
+                    help="read rocprofv3 FETCH_SIZE/WRITE_SIZE passes from DIR for this workload's "
+                         "plan and write DIR/traffic.json")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -256,7 +328,7 @@ def main():
         # reference and the scale for the FETCH_SIZE / WRITE_SIZE counters
         src = torch.ones((512, 512, 512), dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
-        secs = time_runs(torch, lambda: dst.copy_(src), args.steps, args.warmup)
+        secs = time_runs(torch, lambda: st.copy(dst, src), args.steps, args.warmup)
         nbytes = 2.0 * src.numel() * 8
         print(json.dumps({"metric": "device copy GB/s", "value": round(nbytes * args.steps / secs / 1e9, 1),
                           "unit": "GB/s", "bytes_per_launch": nbytes,
@@ -267,6 +339,11 @@ def main():
     w = WORKLOADS[args.workload](torch, st, synth, dtype, _select(args))
     info = w.plan.info()
     log(f"plan: {info}")
+    tkey = [args.workload, dtype, info["kernel"], info["tb"], info["tile_x"], info["tile_y"], info["tile_z"],
+            info["block"], info["workgroups"]]
+    if args.ingest_counters:
+        ingest_counters(args.ingest_counters, tkey, os.path.join(args.ingest_counters, "traffic.json"))
+        return
     secs, value, passes, launch_s, alg = measure(torch, w, args.steps, args.warmup)
     achieved = alg / launch_s / 1e9
     log(f"{value:.1f} Gcell/s, {secs / args.steps * 1e3:.3f} ms/run, {passes} passes of "
@@ -296,6 +373,10 @@ def main():
                      "alg_bytes_per_launch": alg},
         "single_pass_roofline_frac": round(value / (PEAK_HBM_GBS / (2 * BYTES[dtype])), 4),
     }
+    tr = traffic_lookup(tkey)
+    if tr is not None:
+        out["roofline"]["traffic"] = round(tr["traffic_bytes"], 0)
+        out["roofline"]["traffic_GBps"] = round(tr["traffic_bytes"] / launch_s / 1e9, 1)
 
     if not args.no_secondary and args.workload == "heat3d":
         sec = {}

@@ -233,6 +233,17 @@ st_status stencil_adjoint_run(st_plan plan, const void* k, double alpha, const d
                               void* const* ckpts, int64_t every, int64_t steps, void* lambda,
                               void* grad_k, void* seg, void* work, void* stream);
 
+/*
+ * stencil_copy -- plain streaming device copy of `bytes` bytes (one read and
+ * one write of every byte: exactly the traffic one pass of the sweep must
+ * move, so its rate is the achievable-bandwidth reference for the sweep's
+ * roofline; the paper's transfer-time model, Sec. 4.1, makes memory traffic
+ * the dominant cost of a pass).  dst and src: device, 16-byte aligned, not
+ * overlapping.  Asynchronous on `stream`.
+ * Errors: ST_ERR_ARG, ST_ERR_HIP.
+ */
+st_status stencil_copy(void* dst, const void* src, int64_t bytes, void* stream);
+
 /* Thread-local text of the last failure ("" if none). */
 const char* stencil_last_error(void);
 

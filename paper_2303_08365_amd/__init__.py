@@ -19,7 +19,7 @@ __all__ = [
     "StencilError", "Plan", "BatchPlan", "run", "library", "library_path", "build",
     "F64", "F32", "BF16", "BC_ZERO", "BC_PERIODIC", "PLAN_AUTOTUNE", "PLAN_NAIVE",
     "PLAN_VARCOEF", "PLAN_GRAPH", "KERNEL_NAIVE", "KERNEL_STREAM2D", "KERNEL_STREAM3D", "KERNEL_VARCOEF3D",
-    "STATUS", "StencilFn", "varcoef_plan",
+    "STATUS", "StencilFn", "varcoef_plan", "copy",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -96,6 +96,7 @@ def library():
             "stencil_run_ckpt": [P, P, P, P, ctypes.c_double, i64, i64, ctypes.POINTER(P), P],
             "stencil_adjoint_run": [P, P, ctypes.c_double, p_dbl, ctypes.POINTER(P), i64, i64, P, P, P,
                                     P, P],
+            "stencil_copy": [P, P, i64, P],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -310,6 +311,15 @@ class BatchPlan:
         st = (ctypes.c_int64 * n)(*[int(s) for s in steps])
         _check(library().stencil_batch_run(self._h, n, gp, wp, cf, st, _stream_handle(stream)))
         return grids
+
+
+def copy(dst, src, stream=None):
+    """Device copy with the library's streaming kernel (bandwidth reference)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("dst and src differ in size")
+    _check(library().stencil_copy(dst.data_ptr(), src.data_ptr(), nbytes, _stream_handle(stream)))
+    return dst
 
 
 def run(grid, coeffs, offsets, steps: int, bc="zero", plan: Optional[Plan] = None, work=None,

@@ -99,4 +99,7 @@ struct VarcoefArgs {
 };
 hipError_t launch_varcoef(int dtype, bool adjoint, const VarcoefArgs& a, hipStream_t s);
 
+// plain streaming copy (bandwidth reference); 16-byte aligned buffers
+hipError_t launch_copy(void* dst, const void* src, int64_t bytes, int cus, hipStream_t s);
+
 }  // namespace st

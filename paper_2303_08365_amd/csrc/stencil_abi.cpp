@@ -1315,3 +1315,20 @@ extern "C" st_status stencil_adjoint_run(st_plan plan, const void* k, double alp
     if (cur != lambda) ST_HIP(hipMemcpyAsync(lambda, cur, bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(work->lambda)");
     return ST_OK;
 }
+
+// ---------------------------------------------------------------------------
+// bandwidth reference
+// ---------------------------------------------------------------------------
+extern "C" st_status stencil_copy(void* dst, const void* src, int64_t bytes, void* stream) {
+    if (bytes < 0) return fail(ST_ERR_ARG, "bytes = %lld < 0", static_cast<long long>(bytes));
+    if (bytes == 0) return ST_OK;
+    if (!dst || !src) return fail(ST_ERR_ARG, "dst and src are required");
+    if (!aligned16(dst) || !aligned16(src)) return fail(ST_ERR_ARG, "dst and src must be 16-byte aligned");
+    const uintptr_t d = reinterpret_cast<uintptr_t>(dst), s0 = reinterpret_cast<uintptr_t>(src);
+    if (d < s0 + static_cast<uintptr_t>(bytes) && s0 < d + static_cast<uintptr_t>(bytes))
+        return fail(ST_ERR_ARG, "dst and src overlap");
+    if (st_status r = need_device(); r != ST_OK) return r;
+    const hipError_t e = launch_copy(dst, src, bytes, device_cus(), static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "copy launch");
+    return ST_OK;
+}

@@ -215,3 +215,13 @@ def test_varcoef_plan_and_validation():
     assert lib.stencil_adjoint_run(p._h, P(FAKE), 0.1, None, ck, 2, 0, P(FAKE), None, None, P(FAKE + 64), None) == 0
     # constant-weight adjoint refuses k / grad_k
     assert lib.stencil_adjoint_run(q._h, P(FAKE), 0.1, w, None, 0, 3, P(FAKE), None, None, P(FAKE + 64), None) == -3
+
+
+def test_copy_validation():
+    lib = st.library()
+    P = ctypes.c_void_p
+    assert lib.stencil_copy(P(FAKE), P(FAKE + 4096), 0, None) == 0
+    assert lib.stencil_copy(P(FAKE), P(FAKE + 4096), -1, None) == -1
+    assert lib.stencil_copy(None, P(FAKE), 64, None) == -1
+    assert lib.stencil_copy(P(FAKE + 8), P(FAKE + 4096), 64, None) == -1     # misaligned
+    assert lib.stencil_copy(P(FAKE), P(FAKE + 32), 64, None) == -1           # overlap

@@ -192,3 +192,14 @@ def test_unaligned_rows_take_the_scalar_path():
     plan = st.Plan(offs, shape, "f64")
     plan.run(g, list(w), 8)
     check(to_host(g), oracle_ref(u0, offs, w, 8), "f64", 8, "unaligned")
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 48, (1 << 22) + 16 * 7, 3 * (1 << 20) + 5])
+def test_streaming_copy_is_exact(nbytes):
+    import paper_2303_08365_amd as st
+    import torch
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros_like(src)
+    st.copy(dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
