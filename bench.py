@@ -67,15 +67,19 @@ def traffic_lookup(key):
     return None
 
 
-def _counter_means(path, counter):
-    """Mean of `counter` per dispatch, per kernel name, from a rocprofv3 CSV."""
+def _counter_means(directory, counter):
+    """Mean of `counter` per dispatch, per kernel name, from the rocprofv3
+    counter CSV(s) found under `directory`."""
     import csv
+    import glob
     out = {}
-    with open(path) as f:
-        for r in csv.DictReader(f):
-            if r["Counter_Name"] != counter:
-                continue
-            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    paths = sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True))
+    for path in paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
     return {k: sum(v) / len(v) for k, v in out.items()}
 
 
@@ -86,8 +90,8 @@ def ingest_counters(directory, key, out_path):
     copy_bytes = 512 ** 3 * 8
     res = {}
     for counter in ("FETCH_SIZE", "WRITE_SIZE"):
-        st_m = _counter_means(os.path.join(directory, f"stencil_{counter}", "run_counter_collection.csv"), counter)
-        cp_m = _counter_means(os.path.join(directory, f"copy_{counter}", "run_counter_collection.csv"), counter)
+        st_m = _counter_means(os.path.join(directory, f"stencil_{counter}"), counter)
+        cp_m = _counter_means(os.path.join(directory, f"copy_{counter}"), counter)
         cp = [v for k, v in cp_m.items() if "copy_kernel" in k]
         sk = [(k, v) for k, v in st_m.items() if "st::" in k]
         if not cp or not sk:
@@ -157,7 +161,8 @@ def heat3d(torch, st, synth, dtype, select=None, n=512, steps=100, alpha=0.15):
     w.u = torch.from_numpy(synth.uniform_field(shape, seed=0) + mode).to("cuda", _tdt(torch, dtype))
     del mode
     w.work = torch.empty_like(w.u)
-    w.plan = st.Plan(synth.star_offsets(3, 1), shape, dtype, "zero")
+    # fused depth, tile and chunk length come from the library's autotuner
+    w.plan = st.Plan(synth.star_offsets(3, 1), shape, dtype, "zero", autotune=select is None)
     if select:
         w.plan.select(**select)
     w.steps, w.cells, w.dtype = steps, n ** 3, dtype
@@ -207,7 +212,7 @@ def star25(torch, st, synth, dtype, select=None, n=512, steps=50):
     w.coeffs = list(synth.star25_weights(0, "f64" if dtype == "f64" else "f32"))
     w.u = torch.from_numpy(synth.uniform_field(shape, seed=0)).to("cuda", _tdt(torch, dtype))
     w.work = torch.empty_like(w.u)
-    w.plan = st.Plan(synth.star_offsets(3, 4), shape, dtype, "periodic")
+    w.plan = st.Plan(synth.star_offsets(3, 4), shape, dtype, "periodic", autotune=select is None)
     if select:
         w.plan.select(**select)
     w.steps, w.cells, w.dtype = steps, n ** 3, dtype

@@ -36,15 +36,12 @@ template <> struct Storage<float> {
     static __device__ __forceinline__ float round(float v) { return v; }
 };
 // bfloat16 storage, FP32 compute: widen exactly, narrow with round to
-// nearest even (NaN kept quiet).
+// nearest even through gfx950's v_cvt_pk_bf16_f32 (NaN stays a quiet NaN).
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
     return __uint_as_float(static_cast<uint32_t>(b) << 16);
 }
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return static_cast<uint16_t>((u | 0x00400000u) >> 16);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return static_cast<uint16_t>(u >> 16);
+    return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f));
 }
 template <> struct Storage<bf16s> {
     using TC = float;

@@ -79,6 +79,7 @@ struct Stream3DKey {
     int32_t dtype, bc, radius, tbmax, vx, k, nw;
     int32_t fast;  // whole-vector rows (see stream3d_impl.h)
     int32_t late;  // one-plane prefetch issued after step 0 (fewer registers)
+    int32_t ylds;  // step-0 y neighbours through LDS too, the tile's halo rows loaded once
 };
 hipError_t launch_stream3d(const Stream3DKey& k, const Stream3DArgs& a, hipStream_t s);
 bool stream3d_has(const Stream3DKey& k);
@@ -96,6 +97,8 @@ struct VarcoefArgs {
     void* grad;         // adjoint only: dL/dk accumulator (+=), may be null
     int64_t nz, ny, nx;
     double alpha;
+    // filled by launch_varcoef: work-group index -> (row, x block), row -> (z, y)
+    uint32_t nxb, nxb_m, nxb_l, ny_m, ny_l;
 };
 hipError_t launch_varcoef(int dtype, bool adjoint, const VarcoefArgs& a, hipStream_t s);
 

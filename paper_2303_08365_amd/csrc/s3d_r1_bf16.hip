@@ -6,6 +6,7 @@ namespace st {
 namespace s3d {
 static const Entry3 kTable[] = {
     S3D_BC(bf16s, 1, 1, 4, 4, 4), S3D_BC(bf16s, 1, 2, 4, 4, 4),
+    S3D_BCY(bf16s, 1, 2, 4, 4, 8, false),
 };
 }  // namespace s3d
 

@@ -6,6 +6,8 @@ namespace s3d {
 static const Entry3 kTable[] = {
     S3D_BC(float, 4, 1, 4, 2, 8), S3D_BC(float, 4, 1, 4, 1, 16),
     S3D_BC(double, 4, 1, 4, 1, 8), S3D_BC(bf16s, 4, 1, 4, 2, 8),
+    S3D_BCY(float, 4, 1, 4, 2, 8, false), S3D_BCY(float, 4, 1, 4, 1, 16, false),
+    S3D_BCY(double, 4, 1, 4, 1, 8, false), S3D_BCY(bf16s, 4, 1, 4, 2, 8, false),
 };
 }  // namespace s3d
 

@@ -336,17 +336,25 @@ void build_candidates(st_plan_s* p) {
         });
     }
     if (!force_naive && p->ndim == 3 && p->cls == kStar && (p->radius == 1 || p->radius == 4)) {
-        struct V { int vx, k, nw, late; };
+        // ylds: step-0 y neighbours through LDS, the tile's halo rows loaded once
+        struct V { int vx, k, nw, late, ylds; };
         std::vector<V> vs;
         if (p->radius == 1) {
-            // first: the fastest measured on MI355X for 512^3 at depth 2
-            if (p->dtype == kF64) vs = {{2, 4, 8, 0}, {2, 4, 4, 0}, {2, 2, 8, 0}, {2, 4, 8, 1}, {2, 3, 8, 1}};
-            else if (p->dtype == kF32) vs = {{4, 4, 8, 0}, {4, 4, 4, 0}, {4, 2, 8, 0}, {4, 4, 8, 1}, {4, 3, 8, 1}};
-            else vs = {{4, 4, 4, 0}};
+            // first: the fastest measured on MI355X for 512^3 at the default depth
+            if (p->dtype == kF64)
+                vs = {{2, 4, 8, 1, 0}, {2, 4, 8, 0, 0}, {2, 4, 4, 0, 0}, {2, 2, 8, 0, 0}, {2, 3, 8, 1, 0},
+                      {2, 4, 8, 0, 1}, {2, 4, 8, 1, 1}};
+            else if (p->dtype == kF32)
+                vs = {{4, 4, 8, 1, 0}, {4, 4, 8, 0, 0}, {4, 4, 4, 0, 0}, {4, 2, 8, 0, 0}, {4, 3, 8, 1, 0},
+                      {4, 4, 8, 0, 1}, {4, 4, 8, 1, 1}};
+            else
+                vs = {{4, 4, 8, 0, 1}, {4, 4, 4, 0, 0}};
         } else {
-            if (p->dtype == kF64) vs = {{4, 1, 8, 0}};
-            else if (p->dtype == kF32) vs = {{4, 2, 8, 0}, {4, 1, 16, 0}};
-            else vs = {{4, 2, 8, 0}};
+            // radius 4: the y halo through LDS (ylds) loads 2R rows per tile
+            // instead of 2R per wave
+            if (p->dtype == kF64) vs = {{4, 1, 8, 0, 1}, {4, 1, 8, 0, 0}};
+            else if (p->dtype == kF32) vs = {{4, 2, 8, 0, 1}, {4, 1, 16, 0, 1}, {4, 2, 8, 0, 0}, {4, 1, 16, 0, 0}};
+            else vs = {{4, 2, 8, 0, 1}, {4, 2, 8, 0, 0}};
         }
         for (int ch : chunks3) {
             if (ch > p->n[0]) continue;
@@ -358,7 +366,7 @@ void build_candidates(st_plan_s* p) {
                         c.kernel = ST_KERNEL_STREAM3D;
                         c.tb = tb;
                         c.chunk = ch;
-                        c.k3 = Stream3DKey{p->dtype, p->bc, p->radius, tbmax, v.vx, v.k, v.nw, 1, v.late};
+                        c.k3 = Stream3DKey{p->dtype, p->bc, p->radius, tbmax, v.vx, v.k, v.nw, 1, v.late, v.ylds};
                         if (stream3d_has(c.k3) && have_device()) c.occ = stream3d_occupancy(c.k3);
                         Geo3 g;
                         if (stream3d_has(c.k3) && geo3(c, p->n, tb, g)) {
@@ -369,8 +377,11 @@ void build_candidates(st_plan_s* p) {
                 }
             }
         }
-        // measured on MI355X (512^3): two fused steps beat one for radius 1
-        const int want = p->radius == 1 ? 2 : 1;
+        // measured on MI355X (512^3, radius 1): three fused steps for FP64 and
+        // FP32 (680 and 1085 Gcell/s against 588 and 1074 at two); bfloat16
+        // storage halves the bytes, so one step already runs at the HBM rate
+        // (1250 Gcell/s) and deeper fusion is VALU-bound below it
+        const int want = (p->radius == 1 && p->dtype != kBF16) ? 3 : 1;
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
             return (a.tb == want && a.chunk == 0) > (b.tb == want && b.chunk == 0);
         });
@@ -653,7 +664,7 @@ st_status autotune(st_plan_s* p) {
     int best_i = p->sel;
     for (size_t i = 0; i < p->cands.size(); ++i) {
         const Candidate& c = p->cands[i];
-        const int64_t steps = std::max<int64_t>(2, 2 * c.tb);
+        const int64_t steps = std::max<int64_t>(8, 4 * c.tb);
         if (run_steps(p, c, a, b, w, steps, nullptr) != ST_OK) continue;  // warm-up
         hipEventRecord(e0, nullptr);
         st_status r = ST_OK;

@@ -13,8 +13,11 @@
 //     DPP "old" operand of lanes 0 and 63 through readlane;
 //   * y neighbours of step 0: own rows, plus R rows above and R rows below
 //     the wave's rows loaded directly (they are other waves' rows, so the
-//     loads hit in cache); of steps >= 1 (T_b > 1): the edge rows of the
-//     neighbouring waves, exchanged through LDS once per level and plane;
+//     loads hit in cache) -- or, in the YL variants, the edge rows of the
+//     neighbouring waves through LDS, the tile's own 2R halo rows being
+//     loaded once per tile (split over the waves) instead of once per wave;
+//     of steps >= 1 (T_b > 1): the edge rows of the neighbouring waves,
+//     exchanged through LDS once per level and plane;
 //   * z neighbours: queue slots.
 // Loads run P planes ahead of use (P = 3 when 2R+1 is a multiple of 3) and
 // are unconditional: ghost cells (zero rule) are replaced by 0 with selects
@@ -44,7 +47,7 @@ namespace st {
 
 namespace s3d {
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL>
 struct Kern {
     using S = Storage<TS>;
     using TC = typename S::TC;
@@ -61,7 +64,11 @@ struct Kern {
     static constexpr int NP = 6 * R + 1;
     static constexpr int SLOTS = H + 2 * R;              // LDS rows -R .. H+R-1
     static constexpr int BUF_ELEMS = SLOTS * W;
-    static constexpr int LDS_BYTES = TBMAX > 1 ? 2 * BUF_ELEMS * static_cast<int>(sizeof(TC)) : 0;
+    // YL: halo rows of the tile each wave loads (slots beyond 2R repeat the last)
+    static constexpr int HR = YL ? (2 * R + NW - 1) / NW : 0;
+    static constexpr int RROWS = YL ? HR : 2 * R;         // ring rows per prefetch slot
+    static constexpr bool XCH = YL || TBMAX > 1;          // any LDS exchange
+    static constexpr int LDS_BYTES = XCH ? 2 * BUF_ELEMS * static_cast<int>(sizeof(TC)) : 0;
 
     struct Ctx {
         const ST_GLOBAL TS* src;
@@ -73,6 +80,8 @@ struct Kern {
         int64_t zs, ze, zlast; // output planes [zs, ze); last streamed plane
         int64_t ox0, ox1, oy0, oy1;
         int64_t xr_x, xr_y;    // the x-ring element this lane fetches
+        int64_t hy[HR > 0 ? HR : 1];   // YL: grid rows of this wave's halo rows
+        int hslot[HR > 0 ? HR : 1];    // YL: their LDS slots
         int lane, wave;
         TC w[NP];
     };
@@ -103,12 +112,17 @@ struct Kern {
 #pragma unroll
         for (int k = 0; k < K; ++k) load_row(c, zz, c.yw + k, v[k]);
     }
-    static __device__ __forceinline__ void load_ring(const Ctx& c, int64_t zr, TC (&r)[2 * R][VX], TC& xv) {
+    static __device__ __forceinline__ void load_ring(const Ctx& c, int64_t zr, TC (&r)[RROWS][VX], TC& xv) {
         const int64_t zz = fix(zr < c.zlast ? zr : c.zlast, c.nz);
+        if constexpr (YL) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            load_row(c, zz, c.yw - R + j, r[j]);
-            load_row(c, zz, c.yw + K + j, r[R + j]);
+            for (int j = 0; j < HR; ++j) load_row(c, zz, c.hy[j], r[j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                load_row(c, zz, c.yw - R + j, r[j]);
+                load_row(c, zz, c.yw + K + j, r[R + j]);
+            }
         }
         xv = ld1(c.src + (zz * c.ny + fix(c.xr_y, c.ny)) * c.nx + fix(c.xr_x, c.nx));
     }
@@ -127,9 +141,10 @@ struct Kern {
             }
         }
     }
-    static __device__ __forceinline__ void take_ring(const Ctx& c, int64_t z, const TC (&r)[2 * R][VX],
+    static __device__ __forceinline__ void take_ring(const Ctx& c, int64_t z, const TC (&r)[RROWS][VX],
                                                      TC xv, TC (&above)[R][VX], TC (&below)[R][VX],
                                                      TC& xg) {
+        static_assert(!YL, "the YL variants take their halo rows with take_halo");
         const bool zg = ghost(z, c.nz);
 #pragma unroll
         for (int j = 0; j < R; ++j) {
@@ -140,6 +155,20 @@ struct Kern {
                 const bool xe = !FAST && ghost(c.xl + e, c.nx);
                 above[j][e] = (ga || xe) ? TC(0) : r[j][e];
                 below[j][e] = (gb || xe) ? TC(0) : r[R + j][e];
+            }
+        }
+        xg = (zg || ghost(c.xr_y, c.ny) || ghost(c.xr_x, c.nx)) ? TC(0) : xv;
+    }
+    static __device__ __forceinline__ void take_halo(const Ctx& c, int64_t z, const TC (&r)[RROWS][VX],
+                                                     TC xv, TC (&h)[RROWS][VX], TC& xg) {
+        const bool zg = ghost(z, c.nz);
+#pragma unroll
+        for (int j = 0; j < RROWS; ++j) {
+            const bool g = zg || ghost(c.hy[j], c.ny);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const bool xe = !FAST && ghost(c.xl + e, c.nx);
+                h[j][e] = (g || xe) ? TC(0) : r[j][e];
             }
         }
         xg = (zg || ghost(c.xr_y, c.ny) || ghost(c.xr_x, c.nx)) ? TC(0) : xv;
@@ -247,7 +276,7 @@ struct Kern {
     struct State {
         TC q[TBMAX][Q][K][VX];
         TC pf[LATE ? 1 : P][K][VX];  // unused when LATE
-        TC rpf[PR][2 * R][VX];
+        TC rpf[PR][RROWS][VX];
         TC xpf[PR];
     };
 
@@ -258,12 +287,15 @@ struct Kern {
         const int64_t zin = zfirst + it;
         // consume this iteration's slots, then refill them P (PR) planes ahead
         TC above0[R][VX], below0[R][VX], xg;
+        TC halo[RROWS][VX];
         if constexpr (LATE) {
             take_main(c, zin, s.q[0][J], s.q[0][J]);
-            take_ring(c, zin - R, s.rpf[0], s.xpf[0], above0, below0, xg);
+            if constexpr (YL) take_halo(c, zin - R, s.rpf[0], s.xpf[0], halo, xg);
+            else take_ring(c, zin - R, s.rpf[0], s.xpf[0], above0, below0, xg);
         } else {
             take_main(c, zin, s.pf[SM], s.q[0][J]);
-            take_ring(c, zin - R, s.rpf[SR], s.xpf[SR], above0, below0, xg);
+            if constexpr (YL) take_halo(c, zin - R, s.rpf[SR], s.xpf[SR], halo, xg);
+            else take_ring(c, zin - R, s.rpf[SR], s.xpf[SR], above0, below0, xg);
             load_main(c, zin + P, s.pf[SM]);
             load_ring(c, zin + PR - R, s.rpf[SR], s.xpf[SR]);
         }
@@ -273,21 +305,28 @@ struct Kern {
         for (int l = 0; l < TBMAX; ++l) {
             if (l < tb) {
                 TC out[K][VX];
-                if (l == 0) {
+                if (l == 0 && !YL) {
                     compute<J, true>(c, s.q[0], xg, above0, below0, out);
-                    if constexpr (LATE) {
-                        // step 0 no longer needs its oldest plane: load the next one there
-                        load_main(c, zin + 1, s.q[0][(J + 1) % Q]);
-                        load_ring(c, zin + 1 - R, s.rpf[0], s.xpf[0]);
-                    }
                 } else {
-                    TC* buf = lds + ((it * (tb - 1) + (l - 1)) & 1) * BUF_ELEMS;
+                    // exchange the edge rows of this level's centre plane; with
+                    // YL every level's exchange also fills the 2R halo slots
+                    // (step 0: the loaded halo rows, later steps: 0)
+                    const int64_t seq = YL ? it * tb + l : it * (tb - 1) + (l - 1);
+                    TC* buf = lds + (seq & 1) * BUF_ELEMS;
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
                         if (k < R || k >= K - R) {
                             TC* p = buf + (c.wave * K + k + R) * W + c.lane * VX;
 #pragma unroll
                             for (int e = 0; e < VX; ++e) p[e] = s.q[l][CEN][k][e];
+                        }
+                    }
+                    if constexpr (YL) {
+#pragma unroll
+                        for (int j = 0; j < HR; ++j) {
+                            TC* p = buf + c.hslot[j] * W + c.lane * VX;
+#pragma unroll
+                            for (int e = 0; e < VX; ++e) p[e] = l == 0 ? halo[j][e] : TC(0);
                         }
                     }
                     __syncthreads();
@@ -302,7 +341,15 @@ struct Kern {
                             below[j][e] = pb[e];
                         }
                     }
-                    compute<J, false>(c, s.q[l], TC(0), above, below, out);
+                    if (l == 0) compute<J, true>(c, s.q[0], xg, above, below, out);
+                    else compute<J, false>(c, s.q[l], TC(0), above, below, out);
+                }
+                if constexpr (LATE) {
+                    if (l == 0) {
+                        // step 0 no longer needs its oldest plane: load the next one there
+                        load_main(c, zin + 1, s.q[0][(J + 1) % Q]);
+                        load_ring(c, zin + 1 - R, s.rpf[0], s.xpf[0]);
+                    }
                 }
                 const int64_t zc = zin - static_cast<int64_t>(l + 1) * R;
                 finish(c, zc, out);
@@ -364,6 +411,14 @@ struct Kern {
             c.xr_y = c.yw + kr;
             c.xr_x = right && slot < K * R ? c.X0 + W + jr : c.X0 - R + jr;
         }
+        if constexpr (YL) {
+#pragma unroll
+            for (int j = 0; j < HR; ++j) {
+                const int h = c.wave * HR + j < 2 * R ? c.wave * HR + j : 2 * R - 1;
+                c.hslot[j] = h < R ? h : H + h;
+                c.hy[j] = c.Y0 + (c.hslot[j] - R);
+            }
+        }
         c.zs = cz * a.chunk_z;
         c.ze = c.zs + a.chunk_z < c.nz ? c.zs + a.chunk_z : c.nz;
 #pragma unroll
@@ -373,7 +428,7 @@ struct Kern {
         const int64_t nit = (c.ze - c.zs) + 2 * static_cast<int64_t>(R) * tb;
         c.zlast = zfirst + nit - 1;
 
-        if constexpr (TBMAX > 1) {
+        if constexpr (TBMAX > 1 && !YL) {
             // ring rows of every LDS buffer stay 0 (ghost / unused halo)
             for (int i = threadIdx.x; i < 2 * R * W; i += blockDim.x) {
                 const int row = i / W, col = i % W;
@@ -410,30 +465,30 @@ struct Kern {
     }
 };
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL>
 __global__ __launch_bounds__(64 * NW) void stream3d_kernel(const Stream3DArgs a) {
-    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE>;
+    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL>;
     extern __shared__ __align__(16) unsigned char smem[];
     KK::run(a, reinterpret_cast<typename KK::TC*>(smem));
 }
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL>
 void launch(const Stream3DArgs& a, hipStream_t s) {
-    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE>;
+    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL>;
     const int64_t tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
-    hipLaunchKernelGGL((stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE>),
+    hipLaunchKernelGGL((stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL>),
                        dim3(static_cast<unsigned>(tiles)), dim3(64 * NW), KK::LDS_BYTES, s, a);
 }
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE>
-constexpr int lds_of() { return Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE>::LDS_BYTES; }
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL>
+constexpr int lds_of() { return Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL>::LDS_BYTES; }
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL>
 int occ_of() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL>,
                                                      64 * NW,
-                                                     lds_of<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE>()) != hipSuccess)
+                                                     lds_of<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL>()) != hipSuccess)
         n = 0;
     return n;
 }
@@ -443,14 +498,17 @@ template <> constexpr int32_t dtype_of<double>() { return kF64; }
 template <> constexpr int32_t dtype_of<float>() { return kF32; }
 template <> constexpr int32_t dtype_of<bf16s>() { return kBF16; }
 
-#define S3D_ENTRY(TS, R, TBM, VX, K, NW, PER, FAST, LATE)                                              \
-    Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, R, TBM, VX, K, NW, FAST, LATE},      \
-           &launch<TS, R, TBM, VX, K, NW, PER, FAST, LATE>, lds_of<TS, R, TBM, VX, K, NW, PER, FAST, LATE>(), \
-           &occ_of<TS, R, TBM, VX, K, NW, PER, FAST, LATE>}
-#define S3D_BCL(TS, R, TBM, VX, K, NW, LATE)                                                                \
-    S3D_ENTRY(TS, R, TBM, VX, K, NW, false, true, LATE), S3D_ENTRY(TS, R, TBM, VX, K, NW, true, true, LATE), \
-        S3D_ENTRY(TS, R, TBM, VX, K, NW, false, false, LATE), S3D_ENTRY(TS, R, TBM, VX, K, NW, true, false, LATE)
+#define S3D_ENTRY(TS, R, TBM, VX, K, NW, PER, FAST, LATE, YL)                                             \
+    Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, R, TBM, VX, K, NW, FAST, LATE, YL},         \
+           &launch<TS, R, TBM, VX, K, NW, PER, FAST, LATE, YL>,                                                 \
+           lds_of<TS, R, TBM, VX, K, NW, PER, FAST, LATE, YL>(), &occ_of<TS, R, TBM, VX, K, NW, PER, FAST, LATE, YL>}
+#define S3D_BCLY(TS, R, TBM, VX, K, NW, LATE, YL)                                                      \
+    S3D_ENTRY(TS, R, TBM, VX, K, NW, false, true, LATE, YL), S3D_ENTRY(TS, R, TBM, VX, K, NW, true, true, LATE, YL), \
+        S3D_ENTRY(TS, R, TBM, VX, K, NW, false, false, LATE, YL),                                      \
+        S3D_ENTRY(TS, R, TBM, VX, K, NW, true, false, LATE, YL)
+#define S3D_BCL(TS, R, TBM, VX, K, NW, LATE) S3D_BCLY(TS, R, TBM, VX, K, NW, LATE, false)
 #define S3D_BC(TS, R, TBM, VX, K, NW) S3D_BCL(TS, R, TBM, VX, K, NW, false)
+#define S3D_BCY(TS, R, TBM, VX, K, NW, LATE) S3D_BCLY(TS, R, TBM, VX, K, NW, LATE, true)
 
 }  // namespace s3d
 }  // namespace st

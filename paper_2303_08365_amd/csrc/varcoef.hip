@@ -15,12 +15,40 @@
 // (An inner face couples j and j+f: the term 0.5*(u_f-u_j) arises once from
 // the update of j and once, with the opposite sign of the lambda difference,
 // from the update of j+f; a ghost face contributes d kap/d k[j] = 1.)
-// Both kernels are one thread per cell; neighbours come through L1/L2, and
-// work-groups are renumbered so each XCD streams a contiguous range of
-// planes.
+// Both kernels are one thread per cell; a work-group covers 256 consecutive
+// cells of one row (its row and plane come from the work-group index with
+// 32-bit scalar arithmetic, so no lane divides), neighbours come through
+// L1/L2, and work-groups are renumbered so each XCD streams a contiguous range
+// of planes.
 #include "dev_common.h"
 
 namespace st {
+
+// Unsigned 32-bit division by a divisor d fixed per launch, with the
+// multiplier m = floor(2^32 (2^l - d) / d) + 1, l = ceil(log2 d) (the
+// round-up method of Granlund and Montgomery, exact for every 32-bit n).
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t m, uint32_t l) {
+    if (l == 0) return n;
+    const uint32_t t = __umulhi(m, n);
+    return (t + ((n - t) >> 1)) >> (l - 1);
+}
+static void fdiv_init(uint32_t d, uint32_t& m, uint32_t& l) {
+    l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    m = l == 0 ? 0u : static_cast<uint32_t>(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+}
+
+// Work-group b (after the XCD renumbering) covers cells xb*256 .. +255 of
+// row y of plane z, with b = (z*ny + y)*nxb + xb.
+__device__ __forceinline__ bool cell_of(const VarcoefArgs& a, int64_t& x, int64_t& y, int64_t& z) {
+    const uint32_t b = static_cast<uint32_t>(xcd_remap(blockIdx.x, gridDim.x));
+    const uint32_t row = fdiv(b, a.nxb_m, a.nxb_l);
+    const uint32_t zz = fdiv(row, a.ny_m, a.ny_l);
+    x = static_cast<int64_t>(b - row * a.nxb) * 256 + threadIdx.x;
+    y = row - zz * static_cast<uint32_t>(a.ny);
+    z = zz;
+    return x < a.nx;
+}
 
 template <typename TS>
 __global__ __launch_bounds__(256) void varcoef_step_kernel(const VarcoefArgs a) {
@@ -29,11 +57,9 @@ __global__ __launch_bounds__(256) void varcoef_step_kernel(const VarcoefArgs a) 
     const ST_GLOBAL TS* k = gptr<TS>(a.k);
     ST_GLOBAL TS* out = gptr_mut<TS>(a.out);
     const int64_t nz = a.nz, ny = a.ny, nx = a.nx;
-    const int64_t cells = nz * ny * nx;
-    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t i = blk * 256 + threadIdx.x;
-    if (i >= cells) return;
-    const int64_t x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+    int64_t x, y, z;
+    if (!cell_of(a, x, y, z)) return;
+    const int64_t i = (z * ny + y) * nx + x;
     const TC uc = ld1(u + i), kc = ld1(k + i);
     const TC alpha = static_cast<TC>(a.alpha);
     const int64_t dz[6] = {-1, 1, 0, 0, 0, 0}, dy[6] = {0, 0, -1, 1, 0, 0}, dx[6] = {0, 0, 0, 0, -1, 1};
@@ -61,11 +87,9 @@ __global__ __launch_bounds__(256) void varcoef_adjoint_kernel(const VarcoefArgs 
     ST_GLOBAL TS* out = gptr_mut<TS>(a.out);
     ST_GLOBAL TS* g = gptr_mut<TS>(a.grad);
     const int64_t nz = a.nz, ny = a.ny, nx = a.nx;
-    const int64_t cells = nz * ny * nx;
-    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t i = blk * 256 + threadIdx.x;
-    if (i >= cells) return;
-    const int64_t x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+    int64_t x, y, z;
+    if (!cell_of(a, x, y, z)) return;
+    const int64_t i = (z * ny + y) * nx + x;
     const TC uc = ld1(u + i), kc = ld1(k + i), lc = ld1(lam + i);
     const TC alpha = static_cast<TC>(a.alpha);
     const int64_t dz[6] = {-1, 1, 0, 0, 0, 0}, dy[6] = {0, 0, -1, 1, 0, 0}, dx[6] = {0, 0, 0, 0, -1, 1};
@@ -88,11 +112,14 @@ __global__ __launch_bounds__(256) void varcoef_adjoint_kernel(const VarcoefArgs 
     if (a.grad != nullptr) st1(g + i, fma_c(alpha, gacc, ld1(g + i)));
 }
 
-hipError_t launch_varcoef(int dtype, bool adjoint, const VarcoefArgs& a, hipStream_t s) {
-    const int64_t cells = a.nz * a.ny * a.nx;
-    const int64_t blocks = (cells + 255) / 256;
+hipError_t launch_varcoef(int dtype, bool adjoint, const VarcoefArgs& args, hipStream_t s) {
+    const int64_t blocks = args.nz * args.ny * ((args.nx + 255) / 256);
     if (blocks <= 0) return hipSuccess;
     if (blocks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    VarcoefArgs a = args;
+    a.nxb = static_cast<uint32_t>((a.nx + 255) / 256);
+    fdiv_init(a.nxb, a.nxb_m, a.nxb_l);
+    fdiv_init(static_cast<uint32_t>(a.ny), a.ny_m, a.ny_l);
     const dim3 grid(static_cast<unsigned>(blocks)), block(256);
     if (dtype == kF64) {
         if (adjoint) hipLaunchKernelGGL(varcoef_adjoint_kernel<double>, grid, block, 0, s, a);
