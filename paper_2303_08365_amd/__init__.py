@@ -79,6 +79,14 @@ def library():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             raise ImportError(f"libstencil.so is not built at {_LIB_PATH}; run build() first")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 (same
+        # soname as the system one the library links).  Loading torch first
+        # makes the library bind to that copy; loading the system copy first
+        # would leave torch with a second runtime that finds no GPU.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
         i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32

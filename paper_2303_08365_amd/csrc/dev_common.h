@@ -174,6 +174,24 @@ __device__ __forceinline__ float from_lower(float v, float old) {
 __device__ __forceinline__ float from_upper(float v, float old) {
     return __int_as_float(dpp_from_upper_i(__float_as_int(v), __float_as_int(old)));
 }
+// Same with 0 entering at the wave's edge (bound_ctrl): one instruction per
+// dword, no initialisation of the destination.
+__device__ __forceinline__ int dpp_from_lower_z(int v) { return __builtin_amdgcn_mov_dpp(v, kDppWaveShr1, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_from_upper_z(int v) { return __builtin_amdgcn_mov_dpp(v, kDppWaveShl1, 0xF, 0xF, true); }
+__device__ __forceinline__ float from_lower_z(float v) { return __int_as_float(dpp_from_lower_z(__float_as_int(v))); }
+__device__ __forceinline__ float from_upper_z(float v) { return __int_as_float(dpp_from_upper_z(__float_as_int(v))); }
+__device__ __forceinline__ double from_lower_z(double v) {
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = static_cast<uint32_t>(dpp_from_lower_z(static_cast<int>(b)));
+    const uint32_t hi = static_cast<uint32_t>(dpp_from_lower_z(static_cast<int>(b >> 32)));
+    return __longlong_as_double((static_cast<uint64_t>(hi) << 32) | lo);
+}
+__device__ __forceinline__ double from_upper_z(double v) {
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = static_cast<uint32_t>(dpp_from_upper_z(static_cast<int>(b)));
+    const uint32_t hi = static_cast<uint32_t>(dpp_from_upper_z(static_cast<int>(b >> 32)));
+    return __longlong_as_double((static_cast<uint64_t>(hi) << 32) | lo);
+}
 __device__ __forceinline__ double from_lower(double v, double old) {
     const uint64_t b = __double_as_longlong(v), o = __double_as_longlong(old);
     const int lo = dpp_from_lower_i(static_cast<int>(b), static_cast<int>(o));
@@ -203,6 +221,10 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblocks) {
 }
 
 __device__ __forceinline__ int64_t wrap_idx(int64_t i, int64_t n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+__device__ __forceinline__ int32_t wrap_idx(int32_t i, int32_t n) {
     i %= n;
     return i < 0 ? i + n : i;
 }

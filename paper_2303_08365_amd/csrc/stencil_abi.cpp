@@ -343,10 +343,10 @@ void build_candidates(st_plan_s* p) {
             // first: the fastest measured on MI355X for 512^3 at the default depth
             if (p->dtype == kF64)
                 vs = {{2, 4, 8, 1, 0}, {2, 4, 8, 0, 0}, {2, 4, 4, 0, 0}, {2, 2, 8, 0, 0}, {2, 3, 8, 1, 0},
-                      {2, 4, 8, 0, 1}, {2, 4, 8, 1, 1}};
+                      {2, 4, 8, 0, 1}, {2, 4, 8, 1, 1}, {2, 5, 8, 1, 1}};
             else if (p->dtype == kF32)
                 vs = {{4, 4, 8, 1, 0}, {4, 4, 8, 0, 0}, {4, 4, 4, 0, 0}, {4, 2, 8, 0, 0}, {4, 3, 8, 1, 0},
-                      {4, 4, 8, 0, 1}, {4, 4, 8, 1, 1}};
+                      {4, 4, 8, 0, 1}, {4, 4, 8, 1, 1}, {4, 5, 8, 1, 1}};
             else
                 vs = {{4, 4, 8, 0, 1}, {4, 4, 4, 0, 0}};
         } else {

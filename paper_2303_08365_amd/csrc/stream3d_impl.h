@@ -20,9 +20,13 @@
 //     exchanged through LDS once per level and plane;
 //   * z neighbours: queue slots.
 // Loads run P planes ahead of use (P = 3 when 2R+1 is a multiple of 3) and
-// are unconditional: ghost cells (zero rule) are replaced by 0 with selects
-// when the values are consumed, so no branch separates a load from its use
-// and the prefetch stays in flight.
+// are unconditional buffer loads: each row is read through a descriptor whose
+// byte range is that row (the whole plane for the x-ring values), and a row or
+// plane outside the grid gets an empty range, so under the zero rule the
+// hardware returns 0 for every ghost cell -- no masks, no clamped indices, and
+// no branch between a load and its use to drain the prefetch.  Lanes address
+// their columns with a 32-bit offset fixed for the whole run (no 64-bit
+// per-lane pointers), which needs planes below 2 GiB.
 //
 // Tiles.  Step l is exact on the register tile shrunk by (l-1)*R per side
 // (hxa, hya >= R*(tb-1) columns/rows of halo are stored by the neighbour
@@ -71,107 +75,140 @@ struct Kern {
     static constexpr int LDS_BYTES = XCH ? 2 * BUF_ELEMS * static_cast<int>(sizeof(TC)) : 0;
 
     struct Ctx {
-        const ST_GLOBAL TS* src;
-        ST_GLOBAL TS* dst;
-        int64_t nz, ny, nx;
-        int64_t X0, Y0;
-        int64_t xl;            // first column of this lane
-        int64_t yw;            // first row of this wave
-        int64_t zs, ze, zlast; // output planes [zs, ze); last streamed plane
-        int64_t ox0, ox1, oy0, oy1;
-        int64_t xr_x, xr_y;    // the x-ring element this lane fetches
-        int64_t hy[HR > 0 ? HR : 1];   // YL: grid rows of this wave's halo rows
+        const TS* src;
+        int32_t nz, ny, nx;          // every index fits 32 bits: planes are below 2^31 bytes
+        int64_t plane_elems;
+        int32_t X0, Y0;
+        int32_t xl;            // first column of this lane
+        int32_t yw;            // first row of this wave
+        int32_t zs, ze, zlast; // output planes [zs, ze); last streamed plane
+        int32_t ox0, ox1, oy0, oy1;
+        int32_t xr_x, xr_y;    // the x-ring element this lane fetches
+        int32_t hy[HR > 0 ? HR : 1];   // YL: grid rows of this wave's halo rows
         int hslot[HR > 0 ? HR : 1];    // YL: their LDS slots
+        int32_t yk[K];                 // rows this wave loads (wrapped when periodic)
+        int32_t yr[2 * R];             // its ring rows above and below (not YL)
+        int32_t yh[HR > 0 ? HR : 1];   // YL halo rows as loaded
+        uint32_t row_bytes, plane_bytes;
+        uint32_t lo;                   // byte offset of this lane's first column in a row
+        uint32_t eo[VX];               // element offsets (element-wise access)
+        uint32_t xr_off;               // byte offset of the x-ring element in its plane
+        bool xr_xg;                    // that element is an x ghost (zero rule)
+        TS* dstg;                      // output grid (buffer stores)
+        uint32_t so;                   // byte offset of this lane's first column from ox0
+        uint32_t out_bytes;            // bytes of one output row of the tile
         int lane, wave;
         TC w[NP];
     };
 
-    // index rules: periodic wraps, zero clamps (the value is then masked)
-    static __device__ __forceinline__ int64_t fix(int64_t i, int64_t n) {
-        if (PER) return wrap_idx(i, n);
-        return i < 0 ? 0 : (i >= n ? n - 1 : i);
+    static __device__ __forceinline__ bool ghost(int32_t i, int32_t n) {
+        return !PER && static_cast<uint32_t>(i) >= static_cast<uint32_t>(n);  // i < 0 or i >= n
     }
-    static __device__ __forceinline__ bool ghost(int64_t i, int64_t n) {
-        return !PER && (i < 0 || i >= n);
+    static __device__ __forceinline__ int32_t wz(int32_t z, int32_t n) { return PER ? wrap_idx(z, n) : z; }
+
+    // Descriptors: one row of plane zz (or the whole plane); empty outside the
+    // grid.  Periodic indices arrive wrapped.
+    static constexpr int32_t kRsrcWord3 = 0x00020000;  // gfx9: raw 32-bit data
+    static constexpr int32_t kNT = 2;                  // store cache policy: non-temporal
+    static __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const Ctx& c, int32_t zz, int32_t y) {
+        const bool out = ghost(zz, c.nz) || ghost(y, c.ny);
+        const TS* base = out ? c.src : c.src + static_cast<int64_t>(zz) * c.plane_elems + y * c.nx;
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<TS*>(base), 0, out ? 0 : c.row_bytes, kRsrcWord3);
+    }
+    static __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const Ctx& c, int32_t zz) {
+        const bool out = ghost(zz, c.nz);
+        const TS* base = out ? c.src : c.src + static_cast<int64_t>(zz) * c.plane_elems;
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<TS*>(base), 0, out ? 0 : c.plane_bytes, kRsrcWord3);
+    }
+    static __device__ __forceinline__ TC bload1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        if constexpr (sizeof(TS) == 8) {
+            return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+        } else if constexpr (sizeof(TS) == 4) {
+            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+        } else {
+            return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+        }
+    }
+    static __device__ __forceinline__ void bloadv(__amdgpu_buffer_rsrc_t r, uint32_t off, TC (&v)[VX]) {
+        constexpr int kBytes = VX * static_cast<int>(sizeof(TS));
+        static_assert(kBytes % 8 == 0, "vector rows need whole 8-byte units");
+        TS vals[VX];
+        if constexpr (kBytes % 16 == 0) {
+            u32x4 raw[kBytes / 16];
+#pragma unroll
+            for (int i = 0; i < kBytes / 16; ++i)
+                raw[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16 * i, 0, 0));
+            __builtin_memcpy(vals, raw, kBytes);
+        } else {
+            u32x2 raw[kBytes / 8];
+#pragma unroll
+            for (int i = 0; i < kBytes / 8; ++i)
+                raw[i] = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(r, off + 8 * i, 0, 0));
+            __builtin_memcpy(vals, raw, kBytes);
+        }
+#pragma unroll
+        for (int e = 0; e < VX; ++e) v[e] = S::widen(vals[e]);
     }
 
-    static __device__ __forceinline__ void load_row(const Ctx& c, int64_t zz, int64_t y, TC (&v)[VX]) {
-        const ST_GLOBAL TS* row = c.src + (zz * c.ny + fix(y, c.ny)) * c.nx;
+    static __device__ __forceinline__ void load_row(const Ctx& c, int32_t zz, int32_t y, TC (&v)[VX]) {
+        const __amdgpu_buffer_rsrc_t r = row_rsrc(c, zz, y);
         if constexpr (FAST) {
-            ldv<TS, VX>(row + (PER ? wrap_idx(c.xl, c.nx) : c.xl), v);
+            bloadv(r, c.lo, v);
         } else {
 #pragma unroll
-            for (int e = 0; e < VX; ++e) v[e] = ld1(row + fix(c.xl + e, c.nx));
+            for (int e = 0; e < VX; ++e) v[e] = bload1(r, c.eo[e]);
         }
     }
 
     // Loads of one pipeline slot: the wave's K rows of plane zm, and the ring
-    // (2R rows, one x-ring value per lane) of plane zr.
-    static __device__ __forceinline__ void load_main(const Ctx& c, int64_t zm, TC (&v)[K][VX]) {
-        const int64_t zz = fix(zm < c.zlast ? zm : c.zlast, c.nz);
+    // (2R rows, or the wave's share of the tile halo with YL, and one x-ring
+    // value per lane) of plane zr.  Planes past the end of the stream repeat
+    // its last plane (cache hits).
+    static __device__ __forceinline__ void load_main(const Ctx& c, int32_t zm, TC (&v)[K][VX]) {
+        const int32_t zz = wz(zm < c.zlast ? zm : c.zlast, c.nz);
 #pragma unroll
-        for (int k = 0; k < K; ++k) load_row(c, zz, c.yw + k, v[k]);
+        for (int k = 0; k < K; ++k) load_row(c, zz, c.yk[k], v[k]);
     }
-    static __device__ __forceinline__ void load_ring(const Ctx& c, int64_t zr, TC (&r)[RROWS][VX], TC& xv) {
-        const int64_t zz = fix(zr < c.zlast ? zr : c.zlast, c.nz);
+    static __device__ __forceinline__ void load_ring(const Ctx& c, int32_t zr, TC (&r)[RROWS][VX], TC& xv) {
+        const int32_t zz = wz(zr < c.zlast ? zr : c.zlast, c.nz);
         if constexpr (YL) {
 #pragma unroll
-            for (int j = 0; j < HR; ++j) load_row(c, zz, c.hy[j], r[j]);
+            for (int j = 0; j < HR; ++j) load_row(c, zz, c.yh[j], r[j]);
         } else {
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
-                load_row(c, zz, c.yw - R + j, r[j]);
-                load_row(c, zz, c.yw + K + j, r[R + j]);
-            }
+            for (int j = 0; j < 2 * R; ++j) load_row(c, zz, c.yr[j], r[j]);
         }
-        xv = ld1(c.src + (zz * c.ny + fix(c.xr_y, c.ny)) * c.nx + fix(c.xr_x, c.nx));
+        xv = bload1(plane_rsrc(c, zz), c.xr_off);
     }
 
-    // Ghost masks applied when a slot is consumed.
-    static __device__ __forceinline__ void take_main(const Ctx& c, int64_t z, const TC (&v)[K][VX],
-                                                     TC (&q)[K][VX]) {
-        const bool zg = ghost(z, c.nz);
+    // Consuming a slot: the loads already hold 0 on the ghost layer, except
+    // the x-ring value of a lane whose column lies outside the grid (it would
+    // otherwise read the neighbouring row).
+    static __device__ __forceinline__ void take_main(const Ctx&, int32_t, const TC (&v)[K][VX], TC (&q)[K][VX]) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const bool rg = zg || (!FAST && ghost(c.yw + k, c.ny));
+        for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int e = 0; e < VX; ++e) {
-                const bool g = rg || (!FAST && ghost(c.xl + e, c.nx));
-                q[k][e] = g ? TC(0) : v[k][e];
-            }
-        }
+            for (int e = 0; e < VX; ++e) q[k][e] = v[k][e];
     }
-    static __device__ __forceinline__ void take_ring(const Ctx& c, int64_t z, const TC (&r)[RROWS][VX],
-                                                     TC xv, TC (&above)[R][VX], TC (&below)[R][VX],
-                                                     TC& xg) {
+    static __device__ __forceinline__ void take_ring(const Ctx& c, int32_t, const TC (&r)[RROWS][VX], TC xv,
+                                                     TC (&above)[R][VX], TC (&below)[R][VX], TC& xg) {
         static_assert(!YL, "the YL variants take their halo rows with take_halo");
-        const bool zg = ghost(z, c.nz);
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const bool ga = zg || ghost(c.yw - R + j, c.ny);
-            const bool gb = zg || ghost(c.yw + K + j, c.ny);
+        for (int j = 0; j < R; ++j)
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                const bool xe = !FAST && ghost(c.xl + e, c.nx);
-                above[j][e] = (ga || xe) ? TC(0) : r[j][e];
-                below[j][e] = (gb || xe) ? TC(0) : r[R + j][e];
+                above[j][e] = r[j][e];
+                below[j][e] = r[R + j][e];
             }
-        }
-        xg = (zg || ghost(c.xr_y, c.ny) || ghost(c.xr_x, c.nx)) ? TC(0) : xv;
+        xg = c.xr_xg ? TC(0) : xv;
     }
-    static __device__ __forceinline__ void take_halo(const Ctx& c, int64_t z, const TC (&r)[RROWS][VX],
-                                                     TC xv, TC (&h)[RROWS][VX], TC& xg) {
-        const bool zg = ghost(z, c.nz);
+    static __device__ __forceinline__ void take_halo(const Ctx& c, int32_t, const TC (&r)[RROWS][VX], TC xv,
+                                                     TC (&h)[RROWS][VX], TC& xg) {
 #pragma unroll
-        for (int j = 0; j < RROWS; ++j) {
-            const bool g = zg || ghost(c.hy[j], c.ny);
+        for (int j = 0; j < RROWS; ++j)
 #pragma unroll
-            for (int e = 0; e < VX; ++e) {
-                const bool xe = !FAST && ghost(c.xl + e, c.nx);
-                h[j][e] = (g || xe) ? TC(0) : r[j][e];
-            }
-        }
-        xg = (zg || ghost(c.xr_y, c.ny) || ghost(c.xr_x, c.nx)) ? TC(0) : xv;
+            for (int e = 0; e < VX; ++e) h[j][e] = r[j][e];
+        xg = c.xr_xg ? TC(0) : xv;
     }
 
     static __device__ __forceinline__ TC lane_value(TC v, int src_lane) {
@@ -203,10 +240,13 @@ struct Kern {
             TC lft[R], rgt[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const TC ol = LEVEL0 ? lane_value(xg, k * R + j) : TC(0);
-                const TC orr = LEVEL0 ? lane_value(xg, 32 + k * R + j) : TC(0);
-                lft[j] = from_lower(q[CEN][k][VX - R + j], ol);
-                rgt[j] = from_upper(q[CEN][k][j], orr);
+                if constexpr (LEVEL0) {
+                    lft[j] = from_lower(q[CEN][k][VX - R + j], lane_value(xg, k * R + j));
+                    rgt[j] = from_upper(q[CEN][k][j], lane_value(xg, 32 + k * R + j));
+                } else {
+                    lft[j] = from_lower_z(q[CEN][k][VX - R + j]);
+                    rgt[j] = from_upper_z(q[CEN][k][j]);
+                }
             }
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
@@ -241,8 +281,10 @@ struct Kern {
         }
     }
 
-    // Zero rule: ghost cells stay 0; bfloat16 storage rounds every step.
-    static __device__ __forceinline__ void finish(const Ctx& c, int64_t z, TC (&out)[K][VX]) {
+    // Zero rule: ghost cells stay 0; bfloat16 storage rounds every step.  (The
+    // last level skips this: its ghost cells are never stored and the store
+    // rounds.)
+    static __device__ __forceinline__ void finish(const Ctx& c, int32_t z, TC (&out)[K][VX]) {
         const bool zg = ghost(z, c.nz);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -255,36 +297,66 @@ struct Kern {
         }
     }
 
-    static __device__ __forceinline__ void store_plane(const Ctx& c, int64_t z, const TC (&out)[K][VX]) {
-        if (z < c.zs || z >= c.ze) return;
-        if (c.xl < c.ox0 || c.xl >= c.ox1) return;  // lanes are wholly in or out
+    // Buffer stores through a descriptor per row whose range is the tile's
+    // output columns of that row, or empty when the row or plane is not an
+    // output: the hardware drops the rest, so every iteration issues the same
+    // stores with no branch (and the wait counts stay exact).
+    static __device__ __forceinline__ void bstore1(__amdgpu_buffer_rsrc_t r, uint32_t off, TC v) {
+        const TS x = S::narrow(v);
+        if constexpr (sizeof(TS) == 8) {
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, off, 0, kNT);
+        } else if constexpr (sizeof(TS) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, off, 0, kNT);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, x), r, off, 0, kNT);
+        }
+    }
+    static __device__ __forceinline__ void bstorev(__amdgpu_buffer_rsrc_t r, uint32_t off, const TC (&v)[VX]) {
+        constexpr int kBytes = VX * static_cast<int>(sizeof(TS));
+        TS vals[VX];
+#pragma unroll
+        for (int e = 0; e < VX; ++e) vals[e] = S::narrow(v[e]);
+        if constexpr (kBytes % 16 == 0) {
+            u32x4 raw[kBytes / 16];
+            __builtin_memcpy(raw, vals, kBytes);
+#pragma unroll
+            for (int i = 0; i < kBytes / 16; ++i) __builtin_amdgcn_raw_buffer_store_b128(raw[i], r, off + 16 * i, 0, kNT);
+        } else {
+            u32x2 raw[kBytes / 8];
+            __builtin_memcpy(raw, vals, kBytes);
+#pragma unroll
+            for (int i = 0; i < kBytes / 8; ++i) __builtin_amdgcn_raw_buffer_store_b64(raw[i], r, off + 8 * i, 0, kNT);
+        }
+    }
+    static __device__ __forceinline__ void store_plane(const Ctx& c, int32_t z, const TC (&out)[K][VX]) {
+        const bool zok = static_cast<uint32_t>(z - c.zs) < static_cast<uint32_t>(c.ze - c.zs);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int64_t y = c.yw + k;
-            if (y < c.oy0 || y >= c.oy1) continue;
-            ST_GLOBAL TS* row = c.dst + (z * c.ny + y) * c.nx;
+            const int32_t y = c.yw + k;
+            const bool ok = zok && static_cast<uint32_t>(y - c.oy0) < static_cast<uint32_t>(c.oy1 - c.oy0);
+            TS* base = ok ? c.dstg + static_cast<int64_t>(z) * c.plane_elems + y * c.nx + c.ox0 : c.dstg;
+            const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, ok ? c.out_bytes : 0, kRsrcWord3);
             if constexpr (FAST) {
-                stv<TS, VX>(row + c.xl, out[k]);
+                bstorev(r, c.so, out[k]);
             } else {
 #pragma unroll
-                for (int e = 0; e < VX; ++e)
-                    if (c.xl + e < c.nx) st1(row + c.xl + e, out[k][e]);
+                for (int e = 0; e < VX; ++e) bstore1(r, c.so + e * static_cast<uint32_t>(sizeof(TS)), out[k][e]);
             }
         }
     }
 
+    template <int TB>
     struct State {
-        TC q[TBMAX][Q][K][VX];
+        TC q[TB][Q][K][VX];
         TC pf[LATE ? 1 : P][K][VX];  // unused when LATE
         TC rpf[PR][RROWS][VX];
         TC xpf[PR];
     };
 
-    template <int J>
-    static __device__ __forceinline__ void step(const Ctx& c, int tb, int64_t it, int64_t zfirst, State& s,
-                                                TC* lds) {
+    template <int TB, int J>
+    static __device__ __forceinline__ void step(const Ctx& c, int32_t it, int32_t zfirst, State<TB>& s, TC* lds) {
         constexpr int SM = J % P, SR = J % PR;
-        const int64_t zin = zfirst + it;
+        const int32_t zin = zfirst + it;
         // consume this iteration's slots, then refill them P (PR) planes ahead
         TC above0[R][VX], below0[R][VX], xg;
         TC halo[RROWS][VX];
@@ -302,8 +374,8 @@ struct Kern {
 
         constexpr int CEN = (J - R + Q) % Q;
 #pragma unroll
-        for (int l = 0; l < TBMAX; ++l) {
-            if (l < tb) {
+        for (int l = 0; l < TB; ++l) {
+            {
                 TC out[K][VX];
                 if (l == 0 && !YL) {
                     compute<J, true>(c, s.q[0], xg, above0, below0, out);
@@ -311,7 +383,7 @@ struct Kern {
                     // exchange the edge rows of this level's centre plane; with
                     // YL every level's exchange also fills the 2R halo slots
                     // (step 0: the loaded halo rows, later steps: 0)
-                    const int64_t seq = YL ? it * tb + l : it * (tb - 1) + (l - 1);
+                    const int32_t seq = YL ? it * TB + l : it * (TB - 1) + (l - 1);
                     TC* buf = lds + (seq & 1) * BUF_ELEMS;
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
@@ -351,11 +423,11 @@ struct Kern {
                         load_ring(c, zin + 1 - R, s.rpf[0], s.xpf[0]);
                     }
                 }
-                const int64_t zc = zin - static_cast<int64_t>(l + 1) * R;
-                finish(c, zc, out);
-                if (l + 1 == tb) {
+                const int32_t zc = zin - (l + 1) * R;
+                if (l + 1 == TB) {
                     store_plane(c, zc, out);
-                } else if (l + 1 < TBMAX) {
+                } else {
+                    finish(c, zc, out);
 #pragma unroll
                     for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -365,32 +437,34 @@ struct Kern {
         }
     }
 
-    template <int... J>
-    static __device__ __forceinline__ void group(const Ctx& c, int tb, int64_t base, int64_t zfirst, State& s,
-                                                 TC* lds, std::integer_sequence<int, J...>) {
-        (step<J>(c, tb, base + J, zfirst, s, lds), ...);
+    template <int TB, int... J>
+    static __device__ __forceinline__ void group(const Ctx& c, int32_t base, int32_t zfirst, State<TB>& s, TC* lds,
+                                                 std::integer_sequence<int, J...>) {
+        (step<TB, J>(c, base + J, zfirst, s, lds), ...);
     }
-    template <int... J>
-    static __device__ __forceinline__ void tail(const Ctx& c, int tb, int64_t base, int64_t nit, int64_t zfirst,
-                                                State& s, TC* lds, std::integer_sequence<int, J...>) {
-        ((base + J < nit ? step<J>(c, tb, base + J, zfirst, s, lds) : void()), ...);
+    template <int TB, int... J>
+    static __device__ __forceinline__ void tail(const Ctx& c, int32_t base, int32_t nit, int32_t zfirst,
+                                                State<TB>& s, TC* lds, std::integer_sequence<int, J...>) {
+        ((base + J < nit ? step<TB, J>(c, base + J, zfirst, s, lds) : void()), ...);
     }
 
     static __device__ void run(const Stream3DArgs& a, TC* lds) {
         Ctx c;
         c.lane = threadIdx.x & 63;
         c.wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-        const int64_t tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
-        const int64_t item = xcd_remap(blockIdx.x, gridDim.x);
+        // work items < 2^31 (checked by the planner): 32-bit, once per work-group
+        const uint32_t tiles = static_cast<uint32_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
+        const uint32_t item = static_cast<uint32_t>(xcd_remap(blockIdx.x, gridDim.x));
         if (item >= tiles) return;
-        const int64_t tx = item % a.tiles_x;
-        const int64_t ty = (item / a.tiles_x) % a.tiles_y;
-        const int64_t cz = item / (static_cast<int64_t>(a.tiles_x) * a.tiles_y);
-        c.src = gptr<TS>(a.src);
-        c.dst = gptr_mut<TS>(a.dst);
-        c.nz = a.nz;
-        c.ny = a.ny;
-        c.nx = a.nx;
+        const uint32_t txy = item / static_cast<uint32_t>(a.tiles_x);
+        const int32_t tx = static_cast<int32_t>(item - txy * a.tiles_x);
+        const int32_t ty = static_cast<int32_t>(txy % static_cast<uint32_t>(a.tiles_y));
+        const int32_t cz = static_cast<int32_t>(txy / static_cast<uint32_t>(a.tiles_y));
+        c.src = static_cast<const TS*>(a.src);
+        c.nz = static_cast<int32_t>(a.nz);
+        c.ny = static_cast<int32_t>(a.ny);
+        c.nx = static_cast<int32_t>(a.nx);
+        c.plane_elems = a.ny * a.nx;
         c.ox0 = tx * a.out_w;
         c.oy0 = ty * a.out_h;
         c.ox1 = c.ox0 + a.out_w < c.nx ? c.ox0 + a.out_w : c.nx;
@@ -401,8 +475,8 @@ struct Kern {
             c.X0 = c.X0 < 0 ? 0 : (c.X0 + W > c.nx ? c.nx - W : c.X0);
             c.Y0 = c.Y0 < 0 ? 0 : (c.Y0 + H > c.ny ? c.ny - H : c.Y0);
         }
-        c.xl = c.X0 + static_cast<int64_t>(c.lane) * VX;
-        c.yw = c.Y0 + static_cast<int64_t>(c.wave) * K;
+        c.xl = c.X0 + c.lane * VX;
+        c.yw = c.Y0 + c.wave * K;
         {
             const bool right = c.lane >= 32;
             const int slot = right ? c.lane - 32 : c.lane;
@@ -417,18 +491,53 @@ struct Kern {
                 const int h = c.wave * HR + j < 2 * R ? c.wave * HR + j : 2 * R - 1;
                 c.hslot[j] = h < R ? h : H + h;
                 c.hy[j] = c.Y0 + (c.hslot[j] - R);
+                c.yh[j] = PER ? wrap_idx(c.hy[j], c.ny) : c.hy[j];
             }
         }
+#pragma unroll
+        for (int k = 0; k < K; ++k) c.yk[k] = PER ? wrap_idx(c.yw + k, c.ny) : c.yw + k;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            c.yr[j] = PER ? wrap_idx(c.yw - R + j, c.ny) : c.yw - R + j;
+            c.yr[R + j] = PER ? wrap_idx(c.yw + K + j, c.ny) : c.yw + K + j;
+        }
+        c.row_bytes = static_cast<uint32_t>(c.nx) * sizeof(TS);
+        c.plane_bytes = static_cast<uint32_t>(c.plane_elems) * sizeof(TS);
+        // 32-bit offsets: a ghost column or row becomes a huge unsigned offset,
+        // past the end of the descriptor's range
+        c.lo = static_cast<uint32_t>(PER ? wrap_idx(c.xl, c.nx) : c.xl) * sizeof(TS);
+#pragma unroll
+        for (int e = 0; e < VX; ++e)
+            c.eo[e] = static_cast<uint32_t>(PER ? wrap_idx(c.xl + e, c.nx) : c.xl + e) * sizeof(TS);
+        {
+            const int32_t ry = PER ? wrap_idx(c.xr_y, c.ny) : c.xr_y;
+            const int32_t rx = PER ? wrap_idx(c.xr_x, c.nx) : c.xr_x;
+            c.xr_off = static_cast<uint32_t>(ry * c.nx + rx) * sizeof(TS);
+            c.xr_xg = ghost(c.xr_x, c.nx);
+        }
+        c.dstg = static_cast<TS*>(a.dst);
+        c.so = static_cast<uint32_t>(c.xl - c.ox0) * sizeof(TS);
+        c.out_bytes = static_cast<uint32_t>(c.ox1 - c.ox0) * sizeof(TS);
         c.zs = cz * a.chunk_z;
         c.ze = c.zs + a.chunk_z < c.nz ? c.zs + a.chunk_z : c.nz;
 #pragma unroll
         for (int p = 0; p < NP; ++p) c.w[p] = static_cast<TC>(a.w[p]);
+        // one specialised pipeline per fused depth: no run-time level tests
+        // inside the loop
         const int tb = a.tb;
-        const int64_t zfirst = c.zs - static_cast<int64_t>(R) * tb;
-        const int64_t nit = (c.ze - c.zs) + 2 * static_cast<int64_t>(R) * tb;
+        if constexpr (TBMAX >= 4) if (tb == 4) return run_tb<4>(c, lds);
+        if constexpr (TBMAX >= 3) if (tb == 3) return run_tb<3>(c, lds);
+        if constexpr (TBMAX >= 2) if (tb == 2) return run_tb<2>(c, lds);
+        run_tb<1>(c, lds);
+    }
+
+    template <int TB>
+    static __device__ __forceinline__ void run_tb(Ctx& c, TC* lds) {
+        const int32_t zfirst = c.zs - R * TB;
+        const int32_t nit = (c.ze - c.zs) + 2 * R * TB;
         c.zlast = zfirst + nit - 1;
 
-        if constexpr (TBMAX > 1 && !YL) {
+        if constexpr (TB > 1 && !YL) {
             // ring rows of every LDS buffer stay 0 (ghost / unused halo)
             for (int i = threadIdx.x; i < 2 * R * W; i += blockDim.x) {
                 const int row = i / W, col = i % W;
@@ -439,9 +548,9 @@ struct Kern {
             __syncthreads();
         }
 
-        State s;
+        State<TB> s;
 #pragma unroll
-        for (int l = 0; l < TBMAX; ++l)
+        for (int l = 0; l < TB; ++l)
 #pragma unroll
             for (int sl = 0; sl < Q; ++sl)
 #pragma unroll
@@ -458,10 +567,9 @@ struct Kern {
             for (int sp = 0; sp < PR; ++sp) load_ring(c, zfirst + sp - R, s.rpf[sp], s.xpf[sp]);
         }
 
-        int64_t base = 0;
-        for (; base + Q <= nit; base += Q)
-            group(c, tb, base, zfirst, s, lds, std::make_integer_sequence<int, Q>{});
-        tail(c, tb, base, nit, zfirst, s, lds, std::make_integer_sequence<int, Q>{});
+        int32_t base = 0;
+        for (; base + Q <= nit; base += Q) group<TB>(c, base, zfirst, s, lds, std::make_integer_sequence<int, Q>{});
+        tail<TB>(c, base, nit, zfirst, s, lds, std::make_integer_sequence<int, Q>{});
     }
 };
 

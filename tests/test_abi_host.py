@@ -225,3 +225,18 @@ def test_copy_validation():
     assert lib.stencil_copy(None, P(FAKE), 64, None) == -1
     assert lib.stencil_copy(P(FAKE + 8), P(FAKE + 4096), 64, None) == -1     # misaligned
     assert lib.stencil_copy(P(FAKE), P(FAKE + 32), 64, None) == -1           # overlap
+
+
+def test_library_shares_torchs_hip_runtime():
+    # Loading the library before torch must not put a second libamdhip64 in
+    # the process (torch's own runtime would then find no GPU).
+    import subprocess
+    import sys
+    code = ("import paper_2303_08365_amd as st; st.library(); import torch; "
+            "maps = open('/proc/self/maps').read().splitlines(); "
+            "print(sorted({l.split()[-1] for l in maps if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr
+    paths = eval(out.stdout.strip().splitlines()[-1])
+    assert len(paths) == 1, paths
