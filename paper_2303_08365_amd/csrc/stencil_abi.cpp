@@ -342,11 +342,11 @@ void build_candidates(st_plan_s* p) {
         if (p->radius == 1) {
             // first: the fastest measured on MI355X for 512^3 at the default depth
             if (p->dtype == kF64)
-                vs = {{2, 4, 8, 1, 0}, {2, 4, 8, 0, 0}, {2, 4, 4, 0, 0}, {2, 2, 8, 0, 0}, {2, 3, 8, 1, 0},
-                      {2, 4, 8, 0, 1}, {2, 4, 8, 1, 1}, {2, 5, 8, 1, 1}};
+                vs = {{2, 4, 8, 1, 1}, {2, 4, 8, 1, 0}, {2, 4, 8, 0, 0}, {2, 4, 4, 0, 0}, {2, 2, 8, 0, 0},
+                      {2, 3, 8, 1, 0}, {2, 4, 8, 0, 1}, {2, 5, 8, 1, 1}};
             else if (p->dtype == kF32)
-                vs = {{4, 4, 8, 1, 0}, {4, 4, 8, 0, 0}, {4, 4, 4, 0, 0}, {4, 2, 8, 0, 0}, {4, 3, 8, 1, 0},
-                      {4, 4, 8, 0, 1}, {4, 4, 8, 1, 1}, {4, 5, 8, 1, 1}};
+                vs = {{4, 4, 8, 1, 1}, {4, 4, 8, 1, 0}, {4, 4, 8, 0, 0}, {4, 4, 4, 0, 0}, {4, 2, 8, 0, 0},
+                      {4, 3, 8, 1, 0}, {4, 4, 8, 0, 1}, {4, 5, 8, 1, 1}};
             else
                 vs = {{4, 4, 8, 0, 1}, {4, 4, 4, 0, 0}};
         } else {
@@ -377,11 +377,11 @@ void build_candidates(st_plan_s* p) {
                 }
             }
         }
-        // measured on MI355X (512^3, radius 1): three fused steps for FP64 and
-        // FP32 (680 and 1085 Gcell/s against 588 and 1074 at two); bfloat16
-        // storage halves the bytes, so one step already runs at the HBM rate
-        // (1250 Gcell/s) and deeper fusion is VALU-bound below it
-        const int want = (p->radius == 1 && p->dtype != kBF16) ? 3 : 1;
+        // measured on MI355X (512^3, radius 1, 20 steps): four fused steps with
+        // the step-0 halo through LDS and late prefetch for FP64 and FP32 (773
+        // and 1408 Gcell/s; three: 725 and 1290); bfloat16 storage halves the
+        // bytes, so one step already runs near the HBM rate (1380 Gcell/s)
+        const int want = (p->radius == 1 && p->dtype != kBF16) ? 4 : 1;
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
             return (a.tb == want && a.chunk == 0) > (b.tb == want && b.chunk == 0);
         });
