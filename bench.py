@@ -38,13 +38,15 @@ TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def source_hash() -> str:
-    """SHA-256 over the HIP/C++ sources of the library (names and bytes)."""
+    """SHA-256 over the device-code sources of the library (the .hip files and
+    the headers they include; names and bytes).  Host planning code is left
+    out: the launch configuration is part of the lookup key instead."""
     import glob
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2303_08365_amd", "csrc")
     for f in sorted(glob.glob(os.path.join(csrc, "*"))):
-        if f.endswith((".h", ".hip", ".cpp")):
+        if f.endswith((".h", ".hip")):
             h.update(os.path.basename(f).encode())
             with open(f, "rb") as fh:
                 h.update(fh.read())

@@ -263,6 +263,10 @@ struct Geo3 {
 
 bool geo3(const Candidate& c, const int64_t n[3], int tb, Geo3& g) {
     const int vx = c.k3.vx, R = c.k3.radius, H = c.k3.k * c.k3.nw;
+    // the kernel addresses a plane with 32-bit byte offsets and indexes with
+    // 32-bit integers: planes below 2 GiB, every extent below 2^30
+    if (n[1] * n[2] * elem_bytes(c.k3.dtype) >= (int64_t(1) << 31)) return false;
+    if (n[0] >= (int64_t(1) << 30) || n[1] >= (int64_t(1) << 30) || n[2] >= (int64_t(1) << 30)) return false;
     g.hxa = static_cast<int32_t>(round_up(static_cast<int64_t>(R) * (tb - 1), vx));
     g.hya = R * (tb - 1);
     g.out_w = 64 * vx - 2 * g.hxa;

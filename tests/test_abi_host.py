@@ -240,3 +240,14 @@ def test_library_shares_torchs_hip_runtime():
     assert out.returncode == 0, out.stderr
     paths = eval(out.stdout.strip().splitlines()[-1])
     assert len(paths) == 1, paths
+
+
+def test_3d_streaming_needs_planes_below_2gib():
+    # the 3D kernel addresses a plane with 32-bit byte offsets
+    import paper_2303_08365_amd as st
+    offs = synth.star_offsets(3, 1)
+    small = st.Plan(offs, (2, 16000, 16000), "f64")   # 2.048e9 bytes per plane
+    assert any(c["kernel"] == st.KERNEL_STREAM3D for c in small.candidates())
+    big = st.Plan(offs, (2, 16385, 16384), "f64")      # just above 2 GiB
+    assert all(c["kernel"] == st.KERNEL_NAIVE for c in big.candidates())
+    assert big.info()["kernel"] == st.KERNEL_NAIVE
