@@ -341,12 +341,14 @@ def run(grid, coeffs, offsets, steps: int, bc="zero", plan: Optional[Plan] = Non
 _VC_PLANS = {}
 
 
-def varcoef_plan(shape, dtype="f32") -> Plan:
-    """Cached variable-coefficient plan (3D radius-1 star, zero boundary)."""
-    key = (tuple(int(v) for v in shape), _DTYPES[dtype])
+def varcoef_plan(shape, dtype="f32", naive=False) -> Plan:
+    """Cached variable-coefficient plan (3D radius-1 star, zero boundary).
+    naive=True keeps the one-thread-per-cell kernels instead of the
+    z-streaming ones."""
+    key = (tuple(int(v) for v in shape), _DTYPES[dtype], bool(naive))
     if key not in _VC_PLANS:
         star = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
-        _VC_PLANS[key] = Plan(star, key[0], key[1], "zero", varcoef=True)
+        _VC_PLANS[key] = Plan(star, key[0], key[1], "zero", varcoef=True, naive=naive)
     return _VC_PLANS[key]
 
 

@@ -99,8 +99,14 @@ struct VarcoefArgs {
     double alpha;
     // filled by launch_varcoef: work-group index -> (row, x block), row -> (z, y)
     uint32_t nxb, nxb_m, nxb_l, ny_m, ny_l;
+    // streaming kernels: tiles of varcoef_stream_shape(), chunks of planes
+    int32_t tiles_x, tiles_y, chunks_z, chunk_z;
 };
 hipError_t launch_varcoef(int dtype, bool adjoint, const VarcoefArgs& a, hipStream_t s);
+// z-streaming step / adjoint (needs nx >= w, ny >= h, planes below 2 GiB)
+void varcoef_stream_shape(int dtype, bool adjoint, int& w, int& h, int& block);
+hipError_t launch_varcoef_stream(int dtype, bool adjoint, const VarcoefArgs& a, hipStream_t s);
+int varcoef_stream_occupancy(int dtype, bool adjoint);  // work-groups per CU, 0 if unknown
 
 // plain streaming copy (bandwidth reference); 16-byte aligned buffers
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes, int cus, hipStream_t s);

@@ -1219,9 +1219,53 @@ char* at(void* base, int64_t index, size_t bytes) {
     return static_cast<char*>(base) + static_cast<size_t>(index) * bytes;
 }
 
+// The z-streaming kernels need tiles that fit inside the grid, whole vector
+// rows and planes below 2 GiB; ST_PLAN_NAIVE keeps the one-thread-per-cell
+// kernels (the reference form).
+bool varcoef_streamable(const st_plan_s* p, bool adjoint, const void* const* ptrs, int nptr) {
+    if (p->flags & ST_PLAN_NAIVE) return false;
+    int w = 0, h = 0, block = 0;
+    varcoef_stream_shape(p->dtype, adjoint, w, h, block);
+    const int vx = w / 64;
+    if (p->n[2] < w || p->n[1] < h || p->n[2] % vx != 0) return false;
+    if (p->n[1] * p->n[2] * elem_bytes(p->dtype) >= (int64_t(1) << 31) || p->n[0] >= (int64_t(1) << 30)) return false;
+    for (int i = 0; i < nptr; ++i)
+        if (ptrs[i] && !aligned16(ptrs[i])) return false;
+    return true;
+}
+
 st_status varcoef_launch(const st_plan_s* p, bool adjoint, const void* u, const void* k, const void* lam,
                          void* out, void* grad, double alpha, hipStream_t s) {
+    const void* ptrs[5] = {u, k, lam, out, grad};
+    if (varcoef_streamable(p, adjoint, ptrs, 5)) {
+        VarcoefArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.u = u;
+        a.k = k;
+        a.lam = lam;
+        a.out = out;
+        a.grad = grad;
+        a.nz = p->n[0];
+        a.ny = p->n[1];
+        a.nx = p->n[2];
+        a.alpha = alpha;
+        int w = 0, h = 0, block = 0;
+        varcoef_stream_shape(p->dtype, adjoint, w, h, block);
+        a.tiles_x = static_cast<int32_t>(ceil_div(p->n[2], w));
+        a.tiles_y = static_cast<int32_t>(ceil_div(p->n[1], h));
+        const int64_t per_plane = static_cast<int64_t>(a.tiles_x) * a.tiles_y;
+        const int occ = have_device() ? varcoef_stream_occupancy(p->dtype, adjoint) : 0;
+        const int64_t cap = static_cast<int64_t>(device_cus()) * (occ > 0 ? occ : 2);
+        const int64_t chunk = std::min<int64_t>(p->n[0], pick_chunk(p->n[0], per_plane, cap, 2, 8));
+        a.chunk_z = static_cast<int32_t>(chunk);
+        a.chunks_z = static_cast<int32_t>(ceil_div(p->n[0], chunk));
+        if (per_plane * a.chunks_z >= (int64_t(1) << 31)) return fail(ST_ERR_UNSUPPORTED, "too many work-groups");
+        const hipError_t e = launch_varcoef_stream(p->dtype, adjoint, a, s);
+        if (e != hipSuccess) return hip_fail(e, adjoint ? "varcoef adjoint launch" : "varcoef step launch");
+        return ST_OK;
+    }
     VarcoefArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.u = u;
     a.k = k;
     a.lam = lam;

@@ -26,10 +26,10 @@ def _inputs(shape, dtype, seed=0):
     return synth.round_to(u0, dtype), synth.round_to(k, dtype), synth.round_to(y, dtype)
 
 
-def _gpu_forward(u0, k, alpha, steps, dtype, every=0):
+def _gpu_forward(u0, k, alpha, steps, dtype, every=0, naive=False):
     import paper_2303_08365_amd as st
     import torch
-    plan = st.varcoef_plan(u0.shape, dtype)
+    plan = st.varcoef_plan(u0.shape, dtype, naive=naive)
     g = to_device(u0, dtype)
     kk = to_device(k, dtype)
     work = torch.empty_like(g)
@@ -40,9 +40,9 @@ def _gpu_forward(u0, k, alpha, steps, dtype, every=0):
     return g, kk, ck, plan
 
 
-def _gpu_grads(u0, k, y, alpha, steps, dtype, every):
+def _gpu_grads(u0, k, y, alpha, steps, dtype, every, naive=False):
     import torch
-    g, kk, ck, plan = _gpu_forward(u0, k, alpha, steps, dtype, every)
+    g, kk, ck, plan = _gpu_forward(u0, k, alpha, steps, dtype, every, naive)
     uT = to_host(g)
     M = u0.size
     lam = to_device(2.0 * (uT - y) / M, dtype)
@@ -149,3 +149,48 @@ def test_constant_weight_adjoint_is_the_transpose(bc):
     lam = to_device(v, "f64")
     plan7.adjoint(lam, 5, torch.empty_like(lam), coeffs=w7)
     assert oracle.rel_l2(to_host(lam), oracle.sweep_transpose(v, offs7, w7, 5, bc=bc)) <= 1e-12
+
+
+# Shapes the z-streaming kernels take (tiles of 128 columns x 16 / 8 rows fit
+# inside the grid): ragged tiles in x and y, a single tile, wide rows.
+STREAM_SHAPES = [(19, 37, 200), (9, 16, 128), (6, 50, 384)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", STREAM_SHAPES)
+def test_varcoef_streaming_matches_naive_and_oracle(dtype, shape):
+    alpha, steps, every = 0.1, 7, 3
+    u0, k, y = _inputs(shape, dtype, seed=3)
+    print(f"varcoef streaming {dtype} {shape}", flush=True)
+    # forward: the streaming step reproduces the one-thread-per-cell step bit
+    # for bit (same face order; the ghost layer comes from the loads)
+    gs, _, cks, _ = _gpu_forward(u0, k, alpha, steps, dtype, every)
+    gn, _, ckn, _ = _gpu_forward(u0, k, alpha, steps, dtype, every, naive=True)
+    assert np.array_equal(to_host(gs), to_host(gn))
+    for a, b in zip(cks, ckn):
+        assert np.array_equal(to_host(a), to_host(b))
+    ref = oracle.varcoef_forward(u0, k, alpha, steps)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert oracle.rel_l2(to_host(gs), ref) <= tol
+    # adjoint: dL/du0 bit for bit; dL/dk sums its edge terms in another order
+    uT, gu, gk = _gpu_grads(u0, k, y, alpha, steps, dtype, every)
+    _, gun, gkn = _gpu_grads(u0, k, y, alpha, steps, dtype, every, naive=True)
+    assert np.array_equal(gu, gun)
+    assert oracle.rel_l2(gk, gkn) <= (1e-13 if dtype == "f64" else 1e-5)
+    ref_gu, ref_gk = oracle.varcoef_adjoint(u0, k, alpha, steps, 2.0 * (ref - y) / u0.size)
+    e_u, e_k = oracle.rel_l2(gu, ref_gu), oracle.rel_l2(gk, ref_gk)
+    print(f"  dL/du0 {e_u:.2e}  dL/dk {e_k:.2e}", flush=True)
+    if dtype == "f64":
+        assert e_u <= 1e-12 and e_k <= 1e-12
+    else:
+        assert e_u <= TOL_F32_GU and e_k <= TOL_F32_GK
+
+
+def test_varcoef_streaming_checkpoint_interval_does_not_change_a_bit():
+    shape, alpha, steps = (11, 20, 128), 0.1, 10
+    u0, k, y = _inputs(shape, "f64", seed=5)
+    base = _gpu_grads(u0, k, y, alpha, steps, "f64", 1)
+    for every in (3, 10, 25):
+        other = _gpu_grads(u0, k, y, alpha, steps, "f64", every)
+        for a, b in zip(base, other):
+            assert np.array_equal(a, b), every
