@@ -326,7 +326,7 @@ __global__ __launch_bounds__(64 * NW) void varcoef_stream_kernel(const VarcoefAr
 
 // Streaming configuration per precision: (columns per lane, rows per wave, waves)
 template <typename T> struct VcsCfg;
-template <> struct VcsCfg<float> { static constexpr int VX = 2, KF = 4, KA = 2, NW = 4; };
+template <> struct VcsCfg<float> { static constexpr int VX = 4, KF = 4, KA = 2, NW = 4; };
 template <> struct VcsCfg<double> { static constexpr int VX = 2, KF = 4, KA = 2, NW = 4; };
 
 template <typename T>
