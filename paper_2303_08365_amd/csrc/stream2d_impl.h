@@ -21,9 +21,15 @@
 // 32..32+R-1 (right) with the row and reach the DPP "old" operand of lanes 0
 // and 63 through readlane.
 //
-// Rows are prefetched 2R+1 rows ahead with unconditional loads (clamped or
-// wrapped indices); ghost cells of the zero rule become 0 through selects
-// when a row is consumed, so no branch separates a load from its use.
+// Loads.  Rows are prefetched 2R+1 rows ahead with buffer loads through a
+// descriptor whose range is the row; under the zero rule a row outside the
+// grid gets an empty range and a ghost column a 32-bit offset past the row's
+// end, so ghost cells load as 0 -- no masks, no clamped indices, and no
+// branch between a load and its use.  Lanes address their columns with a
+// 32-bit offset fixed for the whole run.  Stores are buffer stores through a
+// descriptor covering the strip's output columns of the row (empty for rows
+// the chunk does not own), so every row issues the same stores.  The pipeline
+// is specialised for the pass's depth (no run-time level tests in the loop).
 //
 // Halo.  Step l is exact on columns [X0 - R + l*R, X0 + W + R - l*R); only
 // the strip interior [X0 + hxa, X0 + W - hxa), hxa >= R*(tb-1), is stored.
@@ -49,50 +55,102 @@ struct Kern {
     static constexpr int Q = 2 * R + 1;  // rows per queue, also the prefetch depth
     static constexpr int W = 64 * VX;     // register strip width
     static constexpr int NP = (CLS == kStar) ? 4 * R + 1 : Q * Q;
+    static constexpr int32_t kRsrcWord3 = 0x00020000;  // gfx9: raw 32-bit data
+    static constexpr int32_t kNT = 2;                  // store cache policy: non-temporal
 
     struct Ctx {
-        const ST_GLOBAL TS* src;
-        ST_GLOBAL TS* dst;
-        int64_t ny, nx;
-        int64_t X0;             // first register column of the strip
-        int64_t xl;             // first column of this lane
-        int64_t xr_x;           // ring column this lane fetches
-        int64_t ys, ye, ylast;  // output rows of the chunk; last streamed row
-        int64_t ofirst, olast;  // output columns [ofirst, olast)
+        const TS* src;
+        TS* dst;
+        int32_t ny, nx;
+        uint32_t row_bytes;
+        int32_t X0;             // first register column of the strip
+        int32_t xl;             // first column of this lane
+        int32_t ys, ye, ylast;  // output rows of the chunk; last streamed row
+        int32_t ylast_w;        // the last streamed row as loaded (wrapped)
+        int32_t ofirst, olast;  // output columns [ofirst, olast)
+        uint32_t lo;            // byte offset of this lane's first column
+        uint32_t eo[VX];        // byte offsets of its columns (element access)
+        uint32_t xr_off;        // byte offset of the ring column this lane fetches
+        uint32_t so, out_bytes; // store: lane offset from ofirst, output row bytes
         int lane;
         TC w[NP];
     };
 
-    static __device__ __forceinline__ int64_t fix(int64_t i, int64_t n) {
-        if (PER) return wrap_idx(i, n);
-        return i < 0 ? 0 : (i >= n ? n - 1 : i);
-    }
-    static __device__ __forceinline__ bool ghost(int64_t i, int64_t n) {
-        return !PER && (i < 0 || i >= n);
+    static __device__ __forceinline__ bool ghost(int32_t i, int32_t n) {
+        return !PER && static_cast<uint32_t>(i) >= static_cast<uint32_t>(n);  // i < 0 or i >= n
     }
 
+    static __device__ __forceinline__ TC bload1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        if constexpr (sizeof(TS) == 8) {
+            return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+        } else if constexpr (sizeof(TS) == 4) {
+            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+        } else {
+            return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+        }
+    }
+    static __device__ __forceinline__ void bloadv(__amdgpu_buffer_rsrc_t r, uint32_t off, TC (&v)[VX]) {
+        constexpr int kBytes = VX * static_cast<int>(sizeof(TS));
+        static_assert(kBytes % 8 == 0, "vector rows need whole 8-byte units");
+        TS vals[VX];
+        if constexpr (kBytes % 16 == 0) {
+            u32x4 raw[kBytes / 16];
+#pragma unroll
+            for (int i = 0; i < kBytes / 16; ++i)
+                raw[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16 * i, 0, 0));
+            __builtin_memcpy(vals, raw, kBytes);
+        } else {
+            u32x2 raw[kBytes / 8];
+#pragma unroll
+            for (int i = 0; i < kBytes / 8; ++i)
+                raw[i] = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(r, off + 8 * i, 0, 0));
+            __builtin_memcpy(vals, raw, kBytes);
+        }
+#pragma unroll
+        for (int e = 0; e < VX; ++e) v[e] = S::widen(vals[e]);
+    }
+    static __device__ __forceinline__ void bstore1(__amdgpu_buffer_rsrc_t r, uint32_t off, TC v) {
+        const TS x = S::narrow(v);
+        if constexpr (sizeof(TS) == 8) {
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, off, 0, kNT);
+        } else if constexpr (sizeof(TS) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, off, 0, kNT);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, x), r, off, 0, kNT);
+        }
+    }
+    static __device__ __forceinline__ void bstorev(__amdgpu_buffer_rsrc_t r, uint32_t off, const TC (&v)[VX]) {
+        constexpr int kBytes = VX * static_cast<int>(sizeof(TS));
+        TS vals[VX];
+#pragma unroll
+        for (int e = 0; e < VX; ++e) vals[e] = S::narrow(v[e]);
+        if constexpr (kBytes % 16 == 0) {
+            u32x4 raw[kBytes / 16];
+            __builtin_memcpy(raw, vals, kBytes);
+#pragma unroll
+            for (int i = 0; i < kBytes / 16; ++i) __builtin_amdgcn_raw_buffer_store_b128(raw[i], r, off + 16 * i, 0, kNT);
+        } else {
+            u32x2 raw[kBytes / 8];
+            __builtin_memcpy(raw, vals, kBytes);
+#pragma unroll
+            for (int i = 0; i < kBytes / 8; ++i) __builtin_amdgcn_raw_buffer_store_b64(raw[i], r, off + 8 * i, 0, kNT);
+        }
+    }
+
+    // Row y (wrapped already when periodic): an empty range outside the grid.
     template <bool FAST>
-    static __device__ __forceinline__ void load_row(const Ctx& c, int64_t y, TC (&v)[VX], TC& xv) {
-        const ST_GLOBAL TS* row = c.src + fix(y < c.ylast ? y : c.ylast, c.ny) * c.nx;
+    static __device__ __forceinline__ void load_row(const Ctx& c, int32_t y, TC (&v)[VX], TC& xv) {
+        const bool out = ghost(y, c.ny);
+        const TS* base = out ? c.src : c.src + static_cast<int64_t>(y) * c.nx;
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<TS*>(base), 0, out ? 0 : c.row_bytes, kRsrcWord3);
         if constexpr (FAST) {
-            ldv<TS, VX>(row + (PER ? wrap_idx(c.xl, c.nx) : c.xl), v);
+            bloadv(r, c.lo, v);
         } else {
 #pragma unroll
-            for (int e = 0; e < VX; ++e) v[e] = ld1(row + fix(c.xl + e, c.nx));
+            for (int e = 0; e < VX; ++e) v[e] = bload1(r, c.eo[e]);
         }
-        xv = ld1(row + fix(c.xr_x, c.nx));
-    }
-
-    template <bool FAST>
-    static __device__ __forceinline__ void take_row(const Ctx& c, int64_t y, const TC (&v)[VX], TC xv,
-                                                    TC (&out)[VX], TC& xo) {
-        const bool yg = ghost(y, c.ny);
-#pragma unroll
-        for (int e = 0; e < VX; ++e) {
-            const bool g = yg || (!FAST && ghost(c.xl + e, c.nx));
-            out[e] = g ? TC(0) : v[e];
-        }
-        xo = (yg || ghost(c.xr_x, c.nx)) ? TC(0) : xv;
+        xv = bload1(r, c.xr_off);
     }
 
     static __device__ __forceinline__ TC lane_value(TC v, int src_lane) {
@@ -108,14 +166,19 @@ struct Kern {
 
     // Neighbours across the lane boundary of one row: lft[k] is column
     // xl - R + k (from lane-1), rgt[k] is column xl + VX + k (from lane+1).
+    // Step 0 takes the strip's outer columns from the ring value; deeper steps
+    // take 0 there (those columns are outside the exact region).
     template <bool LEVEL0>
     static __device__ __forceinline__ void side(const TC (&v)[VX], TC xr, TC (&lft)[R], TC (&rgt)[R]) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const TC ol = LEVEL0 ? lane_value(xr, k) : TC(0);
-            const TC orr = LEVEL0 ? lane_value(xr, 32 + k) : TC(0);
-            lft[k] = from_lower(v[VX - R + k], ol);
-            rgt[k] = from_upper(v[k], orr);
+            if constexpr (LEVEL0) {
+                lft[k] = from_lower(v[VX - R + k], lane_value(xr, k));
+                rgt[k] = from_upper(v[k], lane_value(xr, 32 + k));
+            } else {
+                lft[k] = from_lower_z(v[VX - R + k]);
+                rgt[k] = from_upper_z(v[k]);
+            }
         }
     }
 
@@ -176,8 +239,10 @@ struct Kern {
     }
 
     // Zero rule: ghost rows/columns stay 0; bfloat16 storage rounds every step.
+    // (The last level skips this: ghost cells are never stored and the store
+    // rounds.)
     template <bool FAST>
-    static __device__ __forceinline__ void finish(const Ctx& c, int64_t y, TC (&out)[VX]) {
+    static __device__ __forceinline__ void finish(const Ctx& c, int32_t y, TC (&out)[VX]) {
         const bool yg = ghost(y, c.ny);
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
@@ -187,83 +252,110 @@ struct Kern {
     }
 
     template <bool FAST>
-    static __device__ __forceinline__ void store_row(const Ctx& c, int64_t y, const TC (&out)[VX]) {
-        if (y < c.ys || y >= c.ye) return;
-        if (c.xl < c.ofirst || c.xl >= c.olast) return;  // lanes are wholly in or out
-        ST_GLOBAL TS* row = c.dst + y * c.nx;
+    static __device__ __forceinline__ void store_row(const Ctx& c, int32_t y, const TC (&out)[VX]) {
+        const bool ok = static_cast<uint32_t>(y - c.ys) < static_cast<uint32_t>(c.ye - c.ys);
+        TS* base = ok ? c.dst + static_cast<int64_t>(y) * c.nx + c.ofirst : c.dst;
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, ok ? c.out_bytes : 0, kRsrcWord3);
         if constexpr (FAST) {
-            stv<TS, VX>(row + c.xl, out);
+            bstorev(r, c.so, out);
         } else {
 #pragma unroll
-            for (int e = 0; e < VX; ++e)
-                if (c.xl + e < c.nx) st1(row + c.xl + e, out[e]);
+            for (int e = 0; e < VX; ++e) bstore1(r, c.so + e * static_cast<uint32_t>(sizeof(TS)), out[e]);
         }
     }
 
+    template <int TB>
     struct State {
-        TC q[TBMAX][Q][VX];
+        TC q[TB][Q][VX];
         TC xq[Q];           // step-0 ring values of the queued rows
         TC pf[Q][VX];
         TC pfx[Q];
+        int32_t yl;         // next row to load (wrapped when periodic)
     };
 
-    template <bool FAST, int J>
-    static __device__ __forceinline__ void step(const Ctx& c, int tb, int64_t it, int64_t yfirst, State& s) {
-        const int64_t yin = yfirst + it;
-        take_row<FAST>(c, yin, s.pf[J], s.pfx[J], s.q[0][J], s.xq[J]);
-        load_row<FAST>(c, yin + Q, s.pf[J], s.pfx[J]);
+    static __device__ __forceinline__ int32_t next_row(const Ctx& c, int32_t y) {
+        if constexpr (PER) return y + 1 == c.ny ? 0 : y + 1;
+        return y + 1;
+    }
+
+    template <int TB, bool FAST, int J>
+    static __device__ __forceinline__ void step(const Ctx& c, int32_t it, int32_t yfirst, State<TB>& s) {
+        const int32_t yin = yfirst + it;
 #pragma unroll
-        for (int l = 0; l < TBMAX; ++l) {
-            if (l < tb) {
-                TC out[VX];
-                if (l == 0) {
-                    compute<J, true>(c, s.q[0], s.xq, out);
-                } else {
-                    compute<J, false>(c, s.q[l], s.xq, out);
-                }
-                const int64_t yc = yin - static_cast<int64_t>(l + 1) * R;
+        for (int e = 0; e < VX; ++e) s.q[0][J][e] = s.pf[J][e];
+        s.xq[J] = s.pfx[J];
+        // rows past the end of the stream are never consumed: load the last
+        // streamed row again (a cache hit)
+        load_row<FAST>(c, yin + Q <= c.ylast ? s.yl : c.ylast_w, s.pf[J], s.pfx[J]);
+        s.yl = next_row(c, s.yl);
+#pragma unroll
+        for (int l = 0; l < TB; ++l) {
+            TC out[VX];
+            if (l == 0) compute<J, true>(c, s.q[0], s.xq, out);
+            else compute<J, false>(c, s.q[l], s.xq, out);
+            const int32_t yc = yin - (l + 1) * R;
+            if (l + 1 == TB) {
+                store_row<FAST>(c, yc, out);
+            } else {
                 finish<FAST>(c, yc, out);
-                if (l + 1 == tb) {
-                    store_row<FAST>(c, yc, out);
-                } else if (l + 1 < TBMAX) {
 #pragma unroll
-                    for (int e = 0; e < VX; ++e) s.q[l + 1][J][e] = out[e];
-                }
+                for (int e = 0; e < VX; ++e) s.q[l + 1][J][e] = out[e];
             }
         }
     }
 
-    template <bool FAST, int... J>
-    static __device__ __forceinline__ void group(const Ctx& c, int tb, int64_t base, int64_t yfirst, State& s,
+    template <int TB, bool FAST, int... J>
+    static __device__ __forceinline__ void group(const Ctx& c, int32_t base, int32_t yfirst, State<TB>& s,
                                                  std::integer_sequence<int, J...>) {
-        (step<FAST, J>(c, tb, base + J, yfirst, s), ...);
+        (step<TB, FAST, J>(c, base + J, yfirst, s), ...);
     }
-    template <bool FAST, int... J>
-    static __device__ __forceinline__ void tail(const Ctx& c, int tb, int64_t base, int64_t nit, int64_t yfirst,
-                                                State& s, std::integer_sequence<int, J...>) {
-        ((base + J < nit ? step<FAST, J>(c, tb, base + J, yfirst, s) : void()), ...);
+    template <int TB, bool FAST, int... J>
+    static __device__ __forceinline__ void tail(const Ctx& c, int32_t base, int32_t nit, int32_t yfirst,
+                                                State<TB>& s, std::integer_sequence<int, J...>) {
+        ((base + J < nit ? step<TB, FAST, J>(c, base + J, yfirst, s) : void()), ...);
     }
 
-    template <bool FAST>
-    static __device__ void body(Ctx& c, int tb) {
-        const int64_t yfirst = c.ys - static_cast<int64_t>(R) * tb;
-        const int64_t nit = (c.ye - c.ys) + 2 * static_cast<int64_t>(R) * tb;
+    static __device__ __forceinline__ int32_t wrap_row(const Ctx& c, int32_t y) {
+        return PER ? wrap_idx(y, c.ny) : y;
+    }
+
+    template <int TB, bool FAST>
+    static __device__ void body(Ctx& c) {
+        const int32_t yfirst = c.ys - R * TB;
+        const int32_t nit = (c.ye - c.ys) + 2 * R * TB;
         c.ylast = yfirst + nit - 1;
-        State s;
+        c.ylast_w = wrap_row(c, c.ylast);
+        State<TB> s;
 #pragma unroll
-        for (int l = 0; l < TBMAX; ++l)
+        for (int l = 0; l < TB; ++l)
 #pragma unroll
             for (int sl = 0; sl < Q; ++sl)
 #pragma unroll
                 for (int e = 0; e < VX; ++e) s.q[l][sl][e] = TC(0);
+        s.yl = wrap_row(c, yfirst);
 #pragma unroll
         for (int sl = 0; sl < Q; ++sl) {
             s.xq[sl] = TC(0);
-            load_row<FAST>(c, yfirst + sl, s.pf[sl], s.pfx[sl]);
+            load_row<FAST>(c, yfirst + sl <= c.ylast ? s.yl : c.ylast_w, s.pf[sl], s.pfx[sl]);
+            s.yl = next_row(c, s.yl);
         }
-        int64_t base = 0;
-        for (; base + Q <= nit; base += Q) group<FAST>(c, tb, base, yfirst, s, std::make_integer_sequence<int, Q>{});
-        tail<FAST>(c, tb, base, nit, yfirst, s, std::make_integer_sequence<int, Q>{});
+        int32_t base = 0;
+        for (; base + Q <= nit; base += Q)
+            group<TB, FAST>(c, base, yfirst, s, std::make_integer_sequence<int, Q>{});
+        tail<TB, FAST>(c, base, nit, yfirst, s, std::make_integer_sequence<int, Q>{});
+    }
+
+    // one specialised pipeline per fused depth
+    template <bool FAST>
+    static __device__ void dispatch(Ctx& c, int tb) {
+        if constexpr (TBMAX >= 8) if (tb == 8) return body<8, FAST>(c);
+        if constexpr (TBMAX >= 7) if (tb == 7) return body<7, FAST>(c);
+        if constexpr (TBMAX >= 6) if (tb == 6) return body<6, FAST>(c);
+        if constexpr (TBMAX >= 5) if (tb == 5) return body<5, FAST>(c);
+        if constexpr (TBMAX >= 4) if (tb == 4) return body<4, FAST>(c);
+        if constexpr (TBMAX >= 3) if (tb == 3) return body<3, FAST>(c);
+        if constexpr (TBMAX >= 2) if (tb == 2) return body<2, FAST>(c);
+        body<1, FAST>(c);
     }
 
     static __device__ void run(const Stream2DArgs& a) {
@@ -282,36 +374,46 @@ struct Kern {
         }
         // the descriptor may live in global memory: pin every field to SGPRs
         const int tb = uni(gp->tb);
-        const int64_t tiles_x = uni(static_cast<int64_t>(gp->tiles_x));
-        const int64_t out_w = uni(static_cast<int64_t>(gp->out_w));
-        const int64_t hxa = uni(static_cast<int64_t>(gp->hxa));
-        const int64_t chunk_y = uni(static_cast<int64_t>(gp->chunk_y));
+        const int32_t tiles_x = uni(gp->tiles_x);
+        const int32_t out_w = uni(gp->out_w);
+        const int32_t hxa = uni(gp->hxa);
+        const int32_t chunk_y = uni(gp->chunk_y);
         const bool vec_ok = uni(gp->vec_ok) != 0;
         Ctx c;
-        c.src = gptr<TS>(uni(gp->src));
-        c.dst = gptr_mut<TS>(uni(gp->dst));
-        c.ny = uni(gp->ny);
-        c.nx = uni(gp->nx);
+        c.src = static_cast<const TS*>(uni(gp->src));
+        c.dst = static_cast<TS*>(uni(gp->dst));
+        c.ny = static_cast<int32_t>(uni(gp->ny));
+        c.nx = static_cast<int32_t>(uni(gp->nx));
+        c.row_bytes = static_cast<uint32_t>(c.nx) * sizeof(TS);
         c.lane = lane;
-        const int64_t local = item - uni(gp->tile_begin);
-        const int64_t tx = local % tiles_x, cy = local / tiles_x;
+        const int32_t local = static_cast<int32_t>(item - uni(gp->tile_begin));
+        const int32_t cy = local / tiles_x, tx = local - cy * tiles_x;
         c.ofirst = tx * out_w;
         c.olast = c.ofirst + out_w < c.nx ? c.ofirst + out_w : c.nx;
         c.X0 = c.ofirst - hxa;
         const bool fast = vec_ok && (PER || c.nx >= W);
         if (!PER && fast) c.X0 = c.X0 < 0 ? 0 : (c.X0 + W > c.nx ? c.nx - W : c.X0);
-        c.xl = c.X0 + static_cast<int64_t>(lane) * VX;
+        c.xl = c.X0 + lane * VX;
+        // 32-bit offsets within a row: a ghost column becomes a huge unsigned
+        // offset, past the end of the row's range
+        c.lo = static_cast<uint32_t>(PER ? wrap_idx(c.xl, c.nx) : c.xl) * sizeof(TS);
+#pragma unroll
+        for (int e = 0; e < VX; ++e)
+            c.eo[e] = static_cast<uint32_t>(PER ? wrap_idx(c.xl + e, c.nx) : c.xl + e) * sizeof(TS);
         {
             const bool right = lane >= 32;
             const int k = right ? lane - 32 : lane;
-            c.xr_x = right && k < R ? c.X0 + W + k : c.X0 - R + (k < R ? k : 0);
+            const int32_t xr_x = right && k < R ? c.X0 + W + k : c.X0 - R + (k < R ? k : 0);
+            c.xr_off = static_cast<uint32_t>(PER ? wrap_idx(xr_x, c.nx) : xr_x) * sizeof(TS);
         }
+        c.so = static_cast<uint32_t>(c.xl - c.ofirst) * sizeof(TS);
+        c.out_bytes = static_cast<uint32_t>(c.olast - c.ofirst) * sizeof(TS);
         c.ys = cy * chunk_y;
         c.ye = c.ys + chunk_y < c.ny ? c.ys + chunk_y : c.ny;
 #pragma unroll
         for (int p = 0; p < NP; ++p) c.w[p] = static_cast<TC>(uni(gp->w[p]));
-        if (fast) body<true>(c, tb);
-        else body<false>(c, tb);
+        if (fast) dispatch<true>(c, tb);
+        else dispatch<false>(c, tb);
     }
 };
 
