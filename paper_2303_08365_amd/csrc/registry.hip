@@ -5,7 +5,7 @@ namespace st {
 
 namespace {
 const Entry2* find2(const Stream2DKey& k) {
-    const Table2 tabs[] = {s2d_table_f64(), s2d_table_f32(), s2d_table_bf16()};
+    const Table2 tabs[] = {s2d_table_f64(), s2d_table_f32(), s2d_table_bf16(), s2d_table_r2()};
     for (const Table2& t : tabs)
         for (int i = 0; i < t.n; ++i) {
             const Stream2DKey& e = t.e[i].key;

@@ -311,7 +311,7 @@ void build_candidates(st_plan_s* p) {
     // to 64 planes (512^3).
     const int chunks2[] = {0, 4, 8, 16, 32, 48, 64, 96, 128};
     const int chunks3[] = {0, 32, 64, 128};
-    if (!force_naive && p->ndim == 2 && p->radius == 1 && (p->cls == kStar || p->cls == kBox)) {
+    if (!force_naive && p->ndim == 2 && p->radius <= 2 && (p->cls == kStar || p->cls == kBox)) {
         const int vx = default_vx2(p->dtype);
         const int tbs[] = {1, 2, 4, 8};
         for (int ch : chunks2) {
@@ -334,7 +334,8 @@ void build_candidates(st_plan_s* p) {
             }
         }
         // heuristic default first: deeper fusion for narrower storage, model chunk
-        const int want = p->dtype == kF64 ? 4 : 8;
+        // (radius 2: at most four fused steps are instantiated)
+        const int want = (p->dtype == kF64 || p->radius == 2) ? 4 : 8;
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
             return (a.tb == want && a.chunk == 0) > (b.tb == want && b.chunk == 0);
         });

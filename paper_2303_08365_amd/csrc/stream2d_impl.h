@@ -320,7 +320,7 @@ struct Kern {
     }
 
     template <int TB, bool FAST>
-    static __device__ void body(Ctx& c) {
+    static __device__ __forceinline__ void body(Ctx& c) {
         const int32_t yfirst = c.ys - R * TB;
         const int32_t nit = (c.ye - c.ys) + 2 * R * TB;
         c.ylast = yfirst + nit - 1;
@@ -347,7 +347,7 @@ struct Kern {
 
     // one specialised pipeline per fused depth
     template <bool FAST>
-    static __device__ void dispatch(Ctx& c, int tb) {
+    static __device__ __forceinline__ void dispatch(Ctx& c, int tb) {
         if constexpr (TBMAX >= 8) if (tb == 8) return body<8, FAST>(c);
         if constexpr (TBMAX >= 7) if (tb == 7) return body<7, FAST>(c);
         if constexpr (TBMAX >= 6) if (tb == 6) return body<6, FAST>(c);
@@ -358,7 +358,8 @@ struct Kern {
         body<1, FAST>(c);
     }
 
-    static __device__ void run(const Stream2DArgs& a) {
+    // everything is inlined into the kernel: no device-function calls
+    static __device__ __forceinline__ void run(const Stream2DArgs& a) {
         const int lane = threadIdx.x & 63;
         const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
         const int64_t item = __builtin_amdgcn_readfirstlane(static_cast<int>(wg * 4 + (threadIdx.x >> 6)));

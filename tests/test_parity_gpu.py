@@ -24,11 +24,15 @@ def _weights(offsets, seed=0, dtype="f64"):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("bc", ["zero", "periodic"])
-@pytest.mark.parametrize("pattern", ["star", "box"])
+@pytest.mark.parametrize("pattern", ["star", "box", "star_r2", "box_r2"])
 @pytest.mark.parametrize("shape", [(37, 53), (130, 300), (257, 515)])
 def test_2d_all_candidates_match_oracle(dtype, bc, pattern, shape):
     import paper_2303_08365_amd as st
-    offs = synth.star_offsets(2, 1) if pattern == "star" else synth.box_offsets(2, 1)
+    r = 2 if pattern.endswith("_r2") else 1
+    if r == 2 and dtype == "bf16":
+        pytest.skip("bfloat16 radius-2 2D streaming kernels are switched off: a run of the box/periodic case "
+                    "stopped responding and its cause is not established (the plan uses the one-step kernel)")
+    offs = synth.star_offsets(2, r) if pattern.startswith("star") else synth.box_offsets(2, r)
     w = _weights(offs, 1, dtype)
     steps = 4 if dtype == "bf16" else 11
     u0 = synth.uniform_field(shape, seed=2)
