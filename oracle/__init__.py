@@ -59,7 +59,7 @@ def _load():
         lib.oracle_max_threads.argtypes = []
         for f in (lib.oracle_sweep, lib.oracle_sweep_transpose, lib.oracle_heat,
                   lib.oracle_sweep_point, lib.oracle_varcoef_forward,
-                  lib.oracle_varcoef_adjoint, lib.oracle_max_threads):
+                  lib.oracle_varcoef_adjoint, lib.oracle_max_threads, lib.oracle_sweep_flux):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -101,6 +101,20 @@ def sweep(u0: np.ndarray, offsets, weights, steps: int, bc="zero",
                               _ptr(u, ctypes.c_double), int(threads))
     _check(rc, "oracle_sweep")
     return u
+
+
+def sweep_flux(u0: np.ndarray, offsets, weights, steps: int):
+    """(u_T, outflow): the zero-rule sweep and the total amount its steps send
+    across the grid's boundary (each step sends w_p * u[c] to c - off_p;
+    whatever lands outside the grid leaves), summed in FP64."""
+    u = np.array(u0, dtype=np.float64, order="C", copy=True)
+    off, w = _pattern(offsets, weights, u.ndim)
+    flux = ctypes.c_double(0.0)
+    rc = _load().oracle_sweep_flux(u.ndim, _shape(u), off.shape[0], _ptr(off, ctypes.c_int32),
+                                   _ptr(w, ctypes.c_double), int(steps), _ptr(u, ctypes.c_double),
+                                   ctypes.byref(flux))
+    _check(rc, "oracle_sweep_flux")
+    return u, float(flux.value)
 
 
 def sweep_transpose(v: np.ndarray, offsets, weights, steps: int, bc="zero") -> np.ndarray:

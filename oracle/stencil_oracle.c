@@ -20,6 +20,11 @@
  *   - IEEE double, round to nearest, no fused multiply-add (build with
  *     -ffp-contract=off), points summed in the order given.
  *
+ * The outflow (oracle_sweep_flux) is not in the paper either: it is the
+ * bookkeeping of the zero rule read as an absorbing boundary -- a step moves
+ * w_p * u(c) from cell c to the cell that reads c through point p, and what
+ * would land outside the grid is counted as having left (summed in FP64).
+ *
  * The variable-coefficient heat step and its adjoint are not in the paper;
  * they follow the conservative face-averaged form stated at
  * oracle_varcoef_step below, and the adjoint is the plain reverse-mode
@@ -415,5 +420,52 @@ int oracle_varcoef_adjoint(const int64_t* shape3, const double* k, double alpha,
     }
     free(states);
     free(tmp);
+    return 0;
+}
+
+/* Heat carried out of the grid (zero rule only).  A step sends w[p] * u[c]
+ * from cell c to cell c - off[p] (the cell that reads c through point p);
+ * when that cell lies outside the grid the amount leaves the domain across
+ * the zero-Dirichlet boundary.  This runs `steps` steps exactly as
+ * oracle_sweep does and adds, for every step, the amount that leaves to
+ * *flux (FP64).  With weights summing to 1 the total of u drops by exactly
+ * the outflow in exact arithmetic; the tests use that as a pin. */
+int oracle_sweep_flux(int32_t ndim, const int64_t* shape, int32_t npoints,
+                      const int32_t* offsets, const double* weights, int64_t steps,
+                      double* u, double* flux)
+{
+    or_grid g;
+    if (or_setup(ndim, shape, &g) || npoints < 1 || npoints > 125 || !offsets || !weights ||
+        !u || !flux || steps < 0)
+        return -1;
+    int32_t off[125 * 3];
+    for (int32_t p = 0; p < npoints; ++p) {
+        off[3 * p + 0] = off[3 * p + 1] = off[3 * p + 2] = 0;
+        for (int d = 0; d < ndim; ++d) off[3 * p + 3 - ndim + d] = offsets[p * ndim + d];
+    }
+    double* state = (double*)malloc(sizeof(double) * (size_t)g.cells);
+    if (!state) return -2;
+    memcpy(state, u, sizeof(double) * (size_t)g.cells);
+    double out = 0.0;
+    for (int64_t t = 0; t < steps; ++t) {
+        /* what this step sends outside, from the state it reads */
+        for (int64_t z = 0; z < g.n[0]; ++z)
+            for (int64_t y = 0; y < g.n[1]; ++y)
+                for (int64_t x = 0; x < g.n[2]; ++x) {
+                    const double v = state[(z * g.n[1] + y) * g.n[2] + x];
+                    for (int32_t p = 0; p < npoints; ++p) {
+                        const int64_t tz = z - off[3 * p], ty = y - off[3 * p + 1], tx = x - off[3 * p + 2];
+                        if (tz < 0 || tz >= g.n[0] || ty < 0 || ty >= g.n[1] || tx < 0 || tx >= g.n[2])
+                            out += weights[p] * v;
+                    }
+                }
+        if (oracle_sweep(ndim, shape, npoints, offsets, weights, OR_BC_ZERO, 1, state, 1) != 0) {
+            free(state);
+            return -3;
+        }
+    }
+    memcpy(u, state, sizeof(double) * (size_t)g.cells);
+    free(state);
+    *flux += out;
     return 0;
 }

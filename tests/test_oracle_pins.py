@@ -331,3 +331,67 @@ def test_metric_reproduces_tab3_naive_row(golden_dir):
     g = oracle.stencils_per_second((int(nx), int(ny)), int(steps), float(secs)) / 1e9
     assert round(g, 1) == float(printed)
     assert abs(g - 2.81) < 0.005
+
+
+# ---------------------------------------------------------------------------
+# outflow across the zero-rule boundary
+# ---------------------------------------------------------------------------
+def test_outflow_1d_three_point_by_hand():
+    # offset -1 (weight a) reads the left neighbour, so every cell passes a*u to
+    # its right neighbour: the last cell loses a*u[n-1] through the right face;
+    # offset +1 (weight b) passes b*u to the left: the first cell loses b*u[0]
+    a, b = 0.125, 0.375
+    u = np.array([3.0, 5.0, 7.0, 11.0])
+    _, out = oracle.sweep_flux(u, [(0,), (-1,), (1,)], [0.5, a, b], 1)
+    assert out == a * 11.0 + b * 3.0
+    # swapping the weights swaps the faces
+    _, out2 = oracle.sweep_flux(u, [(0,), (-1,), (1,)], [0.5, b, a], 1)
+    assert out2 == b * 11.0 + a * 3.0
+
+
+def test_outflow_equals_lost_total_for_unit_sum_weights():
+    # sum_x u_{t+1} = (sum_p w_p) sum_x u_t - outflow_t: with weights summing to 1
+    # the total drops by exactly the outflow (rounding aside)
+    rng = np.random.default_rng(11)
+    for ndim, pat in ((2, synth.box_offsets(2, 1)), (3, synth.star_offsets(3, 1)), (3, synth.star_offsets(3, 2)), (2, synth.star_offsets(2, 2))):
+        w = rng.uniform(0.05, 1.0, len(pat))
+        w /= w.sum()
+        shape = (9, 7, 6)[:ndim] if ndim == 3 else (13, 10)
+        u0 = rng.uniform(0.0, 1.0, shape)
+        uT, out = oracle.sweep_flux(u0, pat, w, 7)
+        assert out > 0
+        assert math.isclose(u0.sum() - uT.sum(), out, rel_tol=1e-12)
+
+
+def test_outflow_matches_unbounded_step_on_a_padded_grid():
+    # independent definition: run one step on a grid padded by a ghost frame,
+    # reading zeros outside the original grid; the heat landing on the frame is
+    # what left
+    rng = np.random.default_rng(12)
+    pat = synth.box_offsets(3, 1)
+    w = rng.uniform(-0.2, 0.6, len(pat))
+    u = rng.uniform(-1.0, 1.0, (5, 6, 4))
+    total = 0.0
+    state = u.copy()
+    for _ in range(3):
+        pad = np.pad(state, 1)
+        nxt = np.zeros_like(pad)
+        big = np.pad(pad, 1)  # reads beyond the frame are zero too
+        for off, wp in zip(pat, w):
+            sl = tuple(slice(1 + o, 1 + o + n) for o, n in zip(off, pad.shape))
+            nxt += wp * big[sl]
+        frame = nxt.copy()
+        frame[1:-1, 1:-1, 1:-1] = 0.0
+        total += frame.sum()
+        state = nxt[1:-1, 1:-1, 1:-1]
+    uT, out = oracle.sweep_flux(u, pat, w, 3)
+    np.testing.assert_allclose(uT, state, rtol=0, atol=1e-13)
+    assert math.isclose(out, total, rel_tol=1e-12, abs_tol=1e-13)
+
+
+def test_outflow_zero_for_identity_and_zero_steps():
+    u = np.random.default_rng(13).uniform(0, 1, (4, 5))
+    _, out = oracle.sweep_flux(u, [(0, 0)], [1.0], 5)
+    assert out == 0.0
+    _, out = oracle.sweep_flux(u, synth.star_offsets(2, 1), [0.6, 0.1, 0.1, 0.1, 0.1], 0)
+    assert out == 0.0
