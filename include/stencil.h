@@ -163,6 +163,33 @@ st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs
                       const int64_t* shape, int64_t steps, st_boundary bc, void* stream);
 
 /*
+ * stencil_run_flux -- stencil_run that also keeps account of the heat the
+ * steps carry out of the grid.  Reading the zero ghost layer of Alg. 1
+ * (Sec. 2.1, Eq. 3) as an absorbing boundary, a step moves w_p * u(c) from
+ * cell c to the cell c - off_p that reads c through point p, and what would
+ * land outside the grid has left; with weights summing to 1 the grid's total
+ * then drops by exactly that amount, so total + outflow stays constant up
+ * to rounding and tracks the drift of long FP32 / bfloat16 runs.
+ *   flux    device pointer to ONE double; the outflow of the `steps` steps
+ *           (each step's sum over the state it reads, weights rounded to the
+ *           compute precision, products and sums in FP64) is ADDED to it.
+ *           Under the periodic rule nothing leaves and *flux is not touched.
+ *   other arguments as for stencil_run; the grid ends bit-identical to
+ *           stencil_run's.
+ * The sum is deterministic: partial sums go to a plan-owned device buffer
+ * (allocated by the first call that needs it, which is then not capturable)
+ * and one work-group adds them in a fixed order.  The fused 3D radius-1
+ * kernels (FP64, FP32, bfloat16 default tilings) sum the outflow inside
+ * their passes; every other plan runs one step per pass with a band kernel
+ * over the state each step reads.  ST_PLAN_GRAPH is ignored here (the
+ * launches go to `stream`, or into the caller's capture).
+ * Errors: as stencil_run; ST_ERR_ARG for flux == NULL.
+ */
+st_status stencil_run_flux(st_plan plan, void* grid, void* work, const double* coeffs,
+                           const int64_t* shape, int64_t steps, st_boundary bc, double* flux,
+                           void* stream);
+
+/*
  * stencil_batch_plan -- plan a batch of n independent grids that share the
  * pattern, storage type and boundary but differ in shape and coefficients
  * (an ensemble).  Each pass over all grids is ONE launch: work-groups take

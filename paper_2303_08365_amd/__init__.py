@@ -99,6 +99,7 @@ def library():
             "stencil_plan_candidate": [P, i32, ctypes.POINTER(PlanInfo)],
             "stencil_plan_select": [P, i32, i32, i32],
             "stencil_run": [P, P, P, p_dbl, p_i64, i64, i32, P],
+            "stencil_run_flux": [P, P, P, p_dbl, p_i64, i64, i32, P, P],
             "stencil_batch_plan": [ctypes.POINTER(P), ctypes.POINTER(_Pattern), i32, p_i64, i32, i32, u32],
             "stencil_batch_run": [P, i32, ctypes.POINTER(P), ctypes.POINTER(P), p_dbl, p_i64, P],
             "stencil_run_ckpt": [P, P, P, P, ctypes.c_double, i64, i64, ctypes.POINTER(P), P],
@@ -218,6 +219,27 @@ class Plan:
         _check(library().stencil_run(self._h, grid.data_ptr(),
                                      work.data_ptr() if work is not None else None, w, shp,
                                      int(steps), self.bc, _stream_handle(stream)))
+        return grid
+
+    def run_flux(self, grid, coeffs, steps: int, flux, work=None, stream=None):
+        """``stencil_run_flux``: `steps` steps in place on `grid`, adding the
+        outflow across the zero-rule boundary to `flux` (a one-element FP64
+        device tensor)."""
+        if tuple(grid.shape) != self.shape:
+            raise ValueError(f"grid shape {tuple(grid.shape)} != plan shape {self.shape}")
+        if not grid.is_contiguous() or _tensor_dtype(grid) != self.dtype:
+            raise ValueError("grid must be a contiguous tensor of the plan's dtype")
+        if work is not None and (work.numel() != grid.numel() or work.dtype != grid.dtype):
+            raise ValueError("work must match grid in size and dtype")
+        if flux.numel() != 1 or str(flux.dtype) != "torch.float64" or flux.device != grid.device:
+            raise ValueError("flux must be a one-element float64 tensor on the grid's device")
+        w = _doubles(coeffs)
+        if len(w) != len(self.offsets):
+            raise ValueError("one coefficient per point")
+        shp = (ctypes.c_int64 * len(self.shape))(*self.shape)
+        _check(library().stencil_run_flux(self._h, grid.data_ptr(),
+                                          work.data_ptr() if work is not None else None, w, shp,
+                                          int(steps), self.bc, flux.data_ptr(), _stream_handle(stream)))
         return grid
 
     def _same(self, t, what):

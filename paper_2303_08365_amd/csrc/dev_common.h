@@ -213,6 +213,14 @@ __device__ __forceinline__ double from_upper(double v, double old) {
 // The dispatcher hands work-group b to XCD (b mod 8).  Renumbering so that each
 // XCD receives one contiguous range of logical tiles keeps tiles that share
 // halo cells inside one L2.  A bijection for any count.
+// Sum over the 64 lanes of a wave (butterfly through ds_swizzle/bpermute;
+// every lane's order of additions is fixed, so the result is reproducible).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblocks) {
     constexpr int64_t kXcd = 8;
     const int64_t q = nblocks / kXcd, r = nblocks % kXcd;

@@ -74,12 +74,14 @@ struct Stream3DArgs {
     int32_t vec_ok;
     int32_t tb;
     double w[32];        // canonical-order weights (6R+1 used)
+    double* flux_part;   // outflow variants: one partial sum per wave (work-group * NW + wave)
 };
 struct Stream3DKey {
     int32_t dtype, bc, radius, tbmax, vx, k, nw;
     int32_t fast;  // whole-vector rows (see stream3d_impl.h)
     int32_t late;  // one-plane prefetch issued after step 0 (fewer registers)
     int32_t ylds;  // step-0 y neighbours through LDS too, the tile's halo rows loaded once
+    int32_t flux;  // also sums the outflow of every step of the pass (zero rule)
 };
 hipError_t launch_stream3d(const Stream3DKey& k, const Stream3DArgs& a, hipStream_t s);
 bool stream3d_has(const Stream3DKey& k);
@@ -107,6 +109,23 @@ hipError_t launch_varcoef(int dtype, bool adjoint, const VarcoefArgs& a, hipStre
 void varcoef_stream_shape(int dtype, bool adjoint, int& w, int& h, int& block);
 hipError_t launch_varcoef_stream(int dtype, bool adjoint, const VarcoefArgs& a, hipStream_t s);
 int varcoef_stream_occupancy(int dtype, bool adjoint);  // work-groups per CU, 0 if unknown
+
+// ----------------------------------------------------------------------------
+// outflow across the zero-rule boundary (FP64 partial sums + fixed-order reduce)
+// ----------------------------------------------------------------------------
+struct FluxBandArgs {
+    const void* src;           // the state a step reads
+    int64_t n[3];
+    int32_t npoints;
+    int32_t reach[3];          // largest |offset| along z, y, x
+    int32_t off[kMaxPoints][3];
+    double w[kMaxPoints];      // weights already rounded to compute precision
+};
+constexpr int kFluxBandBlocks = 512;
+// one partial per work-group into part[0 .. nblocks)
+hipError_t launch_flux_band(int dtype, const FluxBandArgs& a, double* part, int nblocks, hipStream_t s);
+// flux[0] += sum of part[0 .. n) (one work-group, fixed order)
+hipError_t launch_flux_reduce(const double* part, int64_t n, double* flux, hipStream_t s);
 
 // plain streaming copy (bandwidth reference); 16-byte aligned buffers
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes, int cus, hipStream_t s);

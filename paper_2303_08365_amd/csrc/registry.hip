@@ -22,7 +22,7 @@ const Entry3* find3(const Stream3DKey& k) {
             const Stream3DKey& e = t.e[i].key;
             if (e.dtype == k.dtype && e.bc == k.bc && e.radius == k.radius && e.tbmax == k.tbmax &&
                 e.vx == k.vx && e.k == k.k && e.nw == k.nw && e.fast == k.fast && e.late == k.late &&
-                e.ylds == k.ylds)
+                e.ylds == k.ylds && e.flux == k.flux)
                 return &t.e[i];
         }
     return nullptr;

@@ -7,6 +7,7 @@ namespace s3d {
 static const Entry3 kTable[] = {
     S3D_BC(bf16s, 1, 1, 4, 4, 4), S3D_BC(bf16s, 1, 2, 4, 4, 4),
     S3D_BCY(bf16s, 1, 2, 4, 4, 8, false),
+    S3D_FLUX(bf16s, 1, 2, 4, 4, 8, false, true),
 };
 }  // namespace s3d
 

@@ -10,6 +10,7 @@ static const Entry3 kTable[] = {
     S3D_BCL(double, 1, 3, 2, 4, 8, true), S3D_BCL(double, 1, 4, 2, 3, 8, true),
     S3D_BCY(double, 1, 2, 2, 4, 8, false), S3D_BCY(double, 1, 3, 2, 4, 8, true),
     S3D_BCY(double, 1, 3, 2, 5, 8, true), S3D_BCY(double, 1, 4, 2, 4, 8, true),
+    S3D_FLUX(double, 1, 4, 2, 4, 8, true, true),
 };
 }  // namespace s3d
 

@@ -178,6 +178,9 @@ struct st_plan_s {
     int32_t sel = 0;
     void* owned_work = nullptr;
     size_t owned_bytes = 0;
+    // outflow runs: partial sums of one pass (per wave or per work-group)
+    double* flux_part = nullptr;
+    int64_t flux_cap = 0;
     // batch
     bool batch = false;
     std::vector<BatchGrid> grids;
@@ -512,7 +515,7 @@ std::vector<int> pass_list(int64_t steps, int tb, bool& copy) {
 }
 
 st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, void* dst,
-                      const double* wcan, int tb, bool vec_ok, hipStream_t s) {
+                      const double* wcan, int tb, bool vec_ok, hipStream_t s, double* fpart = nullptr) {
     hipError_t e = hipSuccess;
     if (c.kernel == ST_KERNEL_NAIVE) {
         NaiveArgs a;
@@ -564,6 +567,7 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
         Stream3DKey key = c.k3;
         key.fast = vec_ok && (p->bc == kPeriodic ||
                               (p->n[2] >= 64 * key.vx && p->n[1] >= static_cast<int64_t>(key.k) * key.nw));
+        key.flux = fpart ? 1 : 0;
         const int lds = stream3d_lds_bytes(key);
         if (lds > device_lds_limit())
             return fail(ST_ERR_UNSUPPORTED, "tiling needs %d bytes of LDS, the device allows %d", lds,
@@ -586,6 +590,7 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
         a.vec_ok = vec_ok ? 1 : 0;
         a.tb = tb;
         for (int i = 0; i < p->npoints; ++i) a.w[i] = wcan[i];
+        a.flux_part = fpart;
         e = launch_stream3d(key, a, s);
         if (e != hipSuccess) return hip_fail(e, "stream3d launch");
         return ST_OK;
@@ -593,9 +598,54 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
     return fail(ST_ERR_UNSUPPORTED, "kernel family %d unknown", c.kernel);
 }
 
-// Run `steps` steps with candidate c: grid -> work -> grid ...
-st_status run_steps(st_plan_s* p, const Candidate& c, void* grid, void* work, const double* wcan,
-                    int64_t steps, hipStream_t s) {
+// Outflow runs (zero rule).  A candidate whose 3D kernel has an
+// outflow-summing twin keeps its fused depth: every wave sums the outflow of
+// its owned cells over the states the pass reads.  Any other candidate runs
+// one step per pass, and the band kernel sums the outflow of each state
+// before the step reads it.  Either way a one-work-group kernel then adds the
+// pass's partial sums to the FP64 accumulator in a fixed order.
+bool flux_fused(const st_plan_s* p, const Candidate& c) {
+    if (c.kernel != ST_KERNEL_STREAM3D || p->bc != kZero) return false;
+    Stream3DKey k = c.k3;
+    k.flux = 1;
+    k.fast = 1;
+    if (!stream3d_has(k)) return false;
+    k.fast = 0;
+    return stream3d_has(k);
+}
+
+// Partial sums one pass of depth tb writes (-1: tiling infeasible).
+int64_t flux_parts(const st_plan_s* p, const Candidate& c, bool fused, int tb) {
+    if (!fused) return kFluxBandBlocks;
+    Geo3 g;
+    if (!geo3(c, p->n, tb, g)) return -1;
+    return static_cast<int64_t>(g.tiles_x) * g.tiles_y * g.chunks_z * c.k3.nw;
+}
+
+st_status ensure_flux_parts(st_plan_s* p, int64_t need, hipStream_t s) {
+    if (need <= p->flux_cap) return ST_OK;
+    if (stream_capturing(s)) return fail(ST_ERR_CAPTURE, "the outflow partial sums need an allocation during capture");
+    if (p->flux_part) {
+        ST_HIP(hipStreamSynchronize(s), "hipStreamSynchronize before regrowing the outflow buffer");
+        hipFree(p->flux_part);
+        p->flux_part = nullptr;
+        p->flux_cap = 0;
+    }
+    if (hipMalloc(&p->flux_part, static_cast<size_t>(need) * sizeof(double)) != hipSuccess) {
+        p->flux_part = nullptr;
+        return fail(ST_ERR_NOMEM, "hipMalloc of %lld outflow partial sums failed", static_cast<long long>(need));
+    }
+    p->flux_cap = need;
+    return ST_OK;
+}
+
+// Run `steps` steps with candidate c: grid -> work -> grid ...  With `flux`
+// (zero rule only), the outflow of every step is also added to flux[0].
+st_status run_steps(st_plan_s* p, const Candidate& c_in, void* grid, void* work, const double* wcan,
+                    int64_t steps, hipStream_t s, double* flux = nullptr) {
+    const bool fused = flux && flux_fused(p, c_in);
+    Candidate c = c_in;
+    if (flux && !fused) c.tb = 1;
     const int tb = (c.kernel == ST_KERNEL_NAIVE) ? 1 : c.tb;
     bool copy = false;
     const std::vector<int> passes = pass_list(steps, tb, copy);
@@ -604,9 +654,38 @@ st_status run_steps(st_plan_s* p, const Candidate& c, void* grid, void* work, co
     const bool vec_ok = (p->n[2] % vx == 0) && aligned16(grid) && aligned16(work);
     void* src = grid;
     void* dst = work;
+    FluxBandArgs fb;
+    if (flux) {
+        int64_t need = 0;
+        for (int t : passes) {
+            const int64_t n = flux_parts(p, c, fused, t);
+            if (n < 0) return fail(ST_ERR_UNSUPPORTED, "3D tiling infeasible");
+            need = std::max(need, n);
+        }
+        if (st_status r = ensure_flux_parts(p, need, s); r != ST_OK) return r;
+        std::memset(&fb, 0, sizeof(fb));
+        for (int d = 0; d < 3; ++d) fb.n[d] = p->n[d];
+        fb.npoints = p->npoints;
+        for (int i = 0; i < p->npoints; ++i) {
+            for (int d = 0; d < 3; ++d) {
+                fb.off[i][d] = p->off[i][d];
+                fb.reach[d] = std::max(fb.reach[d], std::abs(p->off[i][d]));
+            }
+            fb.w[i] = wcan[i];
+        }
+    }
     for (int t : passes) {
-        st_status r = launch_pass(p, c, src, dst, wcan, t, vec_ok, s);
+        if (flux && !fused) {
+            fb.src = src;
+            if (hipError_t e = launch_flux_band(p->dtype, fb, p->flux_part, kFluxBandBlocks, s); e != hipSuccess)
+                return hip_fail(e, "outflow band launch");
+        }
+        st_status r = launch_pass(p, c, src, dst, wcan, t, vec_ok, s, fused ? p->flux_part : nullptr);
         if (r != ST_OK) return r;
+        if (flux) {
+            if (hipError_t e = launch_flux_reduce(p->flux_part, flux_parts(p, c, fused, t), flux, s); e != hipSuccess)
+                return hip_fail(e, "outflow reduce launch");
+        }
         std::swap(src, dst);
     }
     if (copy) ST_HIP(hipMemcpyAsync(grid, work, bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(work->grid)");
@@ -742,6 +821,50 @@ st_status run_graphed(st_plan_s* p, const std::vector<uint64_t>& key, hipStream_
 // ---------------------------------------------------------------------------
 // extern "C"
 // ---------------------------------------------------------------------------
+namespace {
+// Checks shared by stencil_run and stencil_run_flux; picks the work buffer
+// and rounds the weights.  `nothing` is set when there are no steps.
+st_status prepare_run(st_plan_s* plan, void* grid, void*& work, const double* coeffs, const int64_t* shape,
+                      int64_t steps, st_boundary bc, hipStream_t s, double* wcan, bool& nothing) {
+    nothing = false;
+    if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
+    if (plan->batch) return fail(ST_ERR_MISMATCH, "batch plan passed to stencil_run");
+    if (plan->flags & ST_PLAN_VARCOEF)
+        return fail(ST_ERR_MISMATCH, "variable-coefficient plan passed to stencil_run (use stencil_run_ckpt)");
+    if (!shape) return fail(ST_ERR_ARG, "shape is NULL");
+    for (int d = 0; d < plan->ndim; ++d)
+        if (shape[d] != plan->shape[d])
+            return fail(ST_ERR_MISMATCH, "shape[%d] = %lld, plan has %lld", d, static_cast<long long>(shape[d]),
+                        static_cast<long long>(plan->shape[d]));
+    if (bc != plan->bc) return fail(ST_ERR_MISMATCH, "boundary %d, plan has %d", static_cast<int>(bc), plan->bc);
+    if (steps < 0) return fail(ST_ERR_ARG, "steps = %lld < 0", static_cast<long long>(steps));
+    if (steps == 0) {
+        nothing = true;
+        return ST_OK;
+    }
+    if (!grid) return fail(ST_ERR_ARG, "grid is NULL");
+    if (!coeffs) return fail(ST_ERR_ARG, "coeffs is NULL");
+    for (int i = 0; i < plan->npoints; ++i)
+        if (!std::isfinite(coeffs[i])) return fail(ST_ERR_ARG, "coefficient %d is not finite", i);
+    if (st_status r = need_device(); r != ST_OK) return r;
+    const size_t bytes = static_cast<size_t>(plan_cells(plan)) * elem_bytes(plan->dtype);
+    if (!work) {
+        if (!plan->owned_work) {
+            if (stream_capturing(s)) return fail(ST_ERR_CAPTURE, "work == NULL needs an allocation during capture");
+            if (hipMalloc(&plan->owned_work, bytes) != hipSuccess) {
+                plan->owned_work = nullptr;
+                return fail(ST_ERR_NOMEM, "hipMalloc(%zu) for the plan's work buffer failed", bytes);
+            }
+            plan->owned_bytes = bytes;
+        }
+        work = plan->owned_work;
+    }
+    if (work == grid) return fail(ST_ERR_ARG, "work aliases grid");
+    canonical_weights(plan, coeffs, wcan);
+    return ST_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* stencil_last_error(void) { return g_last_error.c_str(); }
@@ -780,6 +903,7 @@ st_status stencil_plan(st_plan* out, const st_pattern* pattern, const int64_t* s
 st_status stencil_plan_destroy(st_plan plan) {
     if (!plan) return ST_OK;
     if (plan->owned_work) hipFree(plan->owned_work);
+    if (plan->flux_part) hipFree(plan->flux_part);
     if (plan->table_dev) hipFree(plan->table_dev);
     if (plan->table_host) hipHostFree(plan->table_host);
     if (plan->table_done) hipEventDestroy(plan->table_done);
@@ -827,39 +951,11 @@ st_status stencil_plan_select(st_plan plan, int32_t kernel, int32_t tb, int32_t 
 
 st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs, const int64_t* shape,
                       int64_t steps, st_boundary bc, void* stream) {
-    if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
-    if (plan->batch) return fail(ST_ERR_MISMATCH, "batch plan passed to stencil_run");
-    if (plan->flags & ST_PLAN_VARCOEF)
-        return fail(ST_ERR_MISMATCH, "variable-coefficient plan passed to stencil_run (use stencil_run_ckpt)");
-    if (!shape) return fail(ST_ERR_ARG, "shape is NULL");
-    for (int d = 0; d < plan->ndim; ++d)
-        if (shape[d] != plan->shape[d])
-            return fail(ST_ERR_MISMATCH, "shape[%d] = %lld, plan has %lld", d, static_cast<long long>(shape[d]),
-                        static_cast<long long>(plan->shape[d]));
-    if (bc != plan->bc) return fail(ST_ERR_MISMATCH, "boundary %d, plan has %d", static_cast<int>(bc), plan->bc);
-    if (steps < 0) return fail(ST_ERR_ARG, "steps = %lld < 0", static_cast<long long>(steps));
-    if (steps == 0) return ST_OK;
-    if (!grid) return fail(ST_ERR_ARG, "grid is NULL");
-    if (!coeffs) return fail(ST_ERR_ARG, "coeffs is NULL");
-    for (int i = 0; i < plan->npoints; ++i)
-        if (!std::isfinite(coeffs[i])) return fail(ST_ERR_ARG, "coefficient %d is not finite", i);
-    if (st_status r = need_device(); r != ST_OK) return r;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const size_t bytes = static_cast<size_t>(plan_cells(plan)) * elem_bytes(plan->dtype);
-    if (!work) {
-        if (!plan->owned_work) {
-            if (stream_capturing(s)) return fail(ST_ERR_CAPTURE, "work == NULL needs an allocation during capture");
-            if (hipMalloc(&plan->owned_work, bytes) != hipSuccess) {
-                plan->owned_work = nullptr;
-                return fail(ST_ERR_NOMEM, "hipMalloc(%zu) for the plan's work buffer failed", bytes);
-            }
-            plan->owned_bytes = bytes;
-        }
-        work = plan->owned_work;
-    }
-    if (work == grid) return fail(ST_ERR_ARG, "work aliases grid");
     double wcan[kMaxPoints];
-    canonical_weights(plan, coeffs, wcan);
+    bool nothing = false;
+    if (st_status r = prepare_run(plan, grid, work, coeffs, shape, steps, bc, s, wcan, nothing); r != ST_OK || nothing)
+        return r;
     std::vector<uint64_t> key;
     if (plan->flags & ST_PLAN_GRAPH) {
         key_push(key, grid);
@@ -870,6 +966,28 @@ st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs
     }
     const Candidate cand = plan->cands[plan->sel];
     return run_graphed(plan, key, s, [&](hipStream_t st) { return run_steps(plan, cand, grid, work, wcan, steps, st); });
+}
+
+st_status stencil_run_flux(st_plan plan, void* grid, void* work, const double* coeffs, const int64_t* shape,
+                           int64_t steps, st_boundary bc, double* flux, void* stream) {
+    if (!flux) return fail(ST_ERR_ARG, "flux is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double wcan[kMaxPoints];
+    bool nothing = false;
+    if (st_status r = prepare_run(plan, grid, work, coeffs, shape, steps, bc, s, wcan, nothing); r != ST_OK || nothing)
+        return r;
+    // a fused candidate of the same depth with an outflow-summing twin
+    // stands in for one without (same states bit for bit: every tiling of a
+    // plan gives the same grid)
+    Candidate cand = plan->cands[plan->sel];
+    if (cand.kernel == ST_KERNEL_STREAM3D && !flux_fused(plan, cand))
+        for (const Candidate& c : plan->cands)
+            if (c.kernel == cand.kernel && c.tb == cand.tb && flux_fused(plan, c)) {
+                cand = c;
+                break;
+            }
+    // a periodic grid has no boundary: nothing leaves
+    return run_steps(plan, cand, grid, work, wcan, steps, s, plan->bc == kZero ? flux : nullptr);
 }
 
 }  // extern "C"

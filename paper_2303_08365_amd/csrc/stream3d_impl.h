@@ -51,7 +51,7 @@ namespace st {
 
 namespace s3d {
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL, bool FLX>
 struct Kern {
     using S = Storage<TS>;
     using TC = typename S::TC;
@@ -99,6 +99,8 @@ struct Kern {
         uint32_t out_bytes;            // bytes of one output row of the tile
         int lane, wave;
         TC w[NP];
+        double* fpart;                 // FLX: this wave's partial outflow slot
+        bool fedge;                    // FLX: the output tile is within R of an x or y face
     };
 
     static __device__ __forceinline__ bool ghost(int32_t i, int32_t n) {
@@ -345,12 +347,52 @@ struct Kern {
         }
     }
 
+    // Outflow (FLX, zero rule): the state a step reads sends w_p * u(c) to
+    // c - off_p; for a star only the points along one axis can cross that
+    // axis's faces.  Points -d (canonical index lo + R - d) send to i + d,
+    // points +d (index hi + d - 1) to i - d.
+    static __device__ __forceinline__ double leave_w(const Ctx& c, int32_t i, int32_t n, int lo, int hi) {
+        double s = 0.0;
+#pragma unroll
+        for (int d = 1; d <= R; ++d) {
+            if (i + d >= n) s += static_cast<double>(c.w[lo + R - d]);
+            if (i - d < 0) s += static_cast<double>(c.w[hi + d - 1]);
+        }
+        return s;
+    }
+    // Adds the outflow of the wave's owned cells of plane z of one state.
+    static __device__ __forceinline__ void flux_add(const Ctx& c, double& fl, int32_t z, const TC (&v)[K][VX]) {
+        if (static_cast<uint32_t>(z - c.zs) >= static_cast<uint32_t>(c.ze - c.zs)) return;
+        const double cz = leave_w(c, z, c.nz, 1, 1 + 5 * R);
+        if (!c.fedge && cz == 0.0) return;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int32_t y = c.yw + k;
+            if (static_cast<uint32_t>(y - c.oy0) >= static_cast<uint32_t>(c.oy1 - c.oy0)) continue;
+            const double czy = cz + leave_w(c, y, c.ny, 1 + R, 1 + 4 * R);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const int32_t x = c.xl + e;
+                const bool own = static_cast<uint32_t>(x - c.ox0) < static_cast<uint32_t>(c.ox1 - c.ox0);
+                const double cc = czy + leave_w(c, x, c.nx, 1 + 2 * R, 1 + 3 * R);
+                acc = own ? fma(static_cast<double>(v[k][e]), cc, acc) : acc;
+            }
+        }
+        fl += acc;
+    }
+    static __device__ __forceinline__ void flux_store(const Ctx& c, double fl) {
+        const double t = wave_sum(fl);
+        if (c.lane == 0) *c.fpart = t;
+    }
+
     template <int TB>
     struct State {
         TC q[TB][Q][K][VX];
         TC pf[LATE ? 1 : P][K][VX];  // unused when LATE
         TC rpf[PR][RROWS][VX];
         TC xpf[PR];
+        double fl;                   // FLX: outflow of this wave's owned cells so far
     };
 
     template <int TB, int J>
@@ -371,6 +413,7 @@ struct Kern {
             load_main(c, zin + P, s.pf[SM]);
             load_ring(c, zin + PR - R, s.rpf[SR], s.xpf[SR]);
         }
+        if constexpr (FLX) flux_add(c, s.fl, zin, s.q[0][J]);  // the pass's input state
 
         constexpr int CEN = (J - R + Q) % Q;
 #pragma unroll
@@ -428,6 +471,7 @@ struct Kern {
                     store_plane(c, zc, out);
                 } else {
                     finish(c, zc, out);
+                    if constexpr (FLX) flux_add(c, s.fl, zc, out);  // state after step l
 #pragma unroll
                     for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -448,14 +492,18 @@ struct Kern {
         ((base + J < nit ? step<TB, J>(c, base + J, zfirst, s, lds) : void()), ...);
     }
 
-    static __device__ void run(const Stream3DArgs& a, TC* lds) {
+    static __device__ __forceinline__ void run(const Stream3DArgs& a, TC* lds) {
         Ctx c;
         c.lane = threadIdx.x & 63;
         c.wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
         // work items < 2^31 (checked by the planner): 32-bit, once per work-group
         const uint32_t tiles = static_cast<uint32_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
         const uint32_t item = static_cast<uint32_t>(xcd_remap(blockIdx.x, gridDim.x));
-        if (item >= tiles) return;
+        if constexpr (FLX) c.fpart = a.flux_part + static_cast<int64_t>(blockIdx.x) * NW + c.wave;
+        if (item >= tiles) {
+            if constexpr (FLX) flux_store(c, 0.0);
+            return;
+        }
         const uint32_t txy = item / static_cast<uint32_t>(a.tiles_x);
         const int32_t tx = static_cast<int32_t>(item - txy * a.tiles_x);
         const int32_t ty = static_cast<int32_t>(txy % static_cast<uint32_t>(a.tiles_y));
@@ -520,6 +568,7 @@ struct Kern {
         c.out_bytes = static_cast<uint32_t>(c.ox1 - c.ox0) * sizeof(TS);
         c.zs = cz * a.chunk_z;
         c.ze = c.zs + a.chunk_z < c.nz ? c.zs + a.chunk_z : c.nz;
+        c.fedge = c.ox0 < R || c.ox1 > c.nx - R || c.oy0 < R || c.oy1 > c.ny - R;
 #pragma unroll
         for (int p = 0; p < NP; ++p) c.w[p] = static_cast<TC>(a.w[p]);
         // one specialised pipeline per fused depth: no run-time level tests
@@ -549,6 +598,7 @@ struct Kern {
         }
 
         State<TB> s;
+        s.fl = 0.0;
 #pragma unroll
         for (int l = 0; l < TB; ++l)
 #pragma unroll
@@ -570,33 +620,34 @@ struct Kern {
         int32_t base = 0;
         for (; base + Q <= nit; base += Q) group<TB>(c, base, zfirst, s, lds, std::make_integer_sequence<int, Q>{});
         tail<TB>(c, base, nit, zfirst, s, lds, std::make_integer_sequence<int, Q>{});
+        if constexpr (FLX) flux_store(c, s.fl);
     }
 };
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL, bool FLX>
 __global__ __launch_bounds__(64 * NW) void stream3d_kernel(const Stream3DArgs a) {
-    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL>;
+    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL, FLX>;
     extern __shared__ __align__(16) unsigned char smem[];
     KK::run(a, reinterpret_cast<typename KK::TC*>(smem));
 }
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL, bool FLX>
 void launch(const Stream3DArgs& a, hipStream_t s) {
-    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL>;
+    using KK = Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL, FLX>;
     const int64_t tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
-    hipLaunchKernelGGL((stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL>),
+    hipLaunchKernelGGL((stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL, FLX>),
                        dim3(static_cast<unsigned>(tiles)), dim3(64 * NW), KK::LDS_BYTES, s, a);
 }
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL>
-constexpr int lds_of() { return Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL>::LDS_BYTES; }
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL, bool FLX>
+constexpr int lds_of() { return Kern<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL, FLX>::LDS_BYTES; }
 
-template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL>
+template <typename TS, int R, int TBMAX, int VX, int K, int NW, bool PER, bool FAST, bool LATE, bool YL, bool FLX>
 int occ_of() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream3d_kernel<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL, FLX>,
                                                      64 * NW,
-                                                     lds_of<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL>()) != hipSuccess)
+                                                     lds_of<TS, R, TBMAX, VX, K, NW, PER, FAST, LATE, YL, FLX>()) != hipSuccess)
         n = 0;
     return n;
 }
@@ -606,17 +657,22 @@ template <> constexpr int32_t dtype_of<double>() { return kF64; }
 template <> constexpr int32_t dtype_of<float>() { return kF32; }
 template <> constexpr int32_t dtype_of<bf16s>() { return kBF16; }
 
-#define S3D_ENTRY(TS, R, TBM, VX, K, NW, PER, FAST, LATE, YL)                                             \
-    Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, R, TBM, VX, K, NW, FAST, LATE, YL},         \
-           &launch<TS, R, TBM, VX, K, NW, PER, FAST, LATE, YL>,                                                 \
-           lds_of<TS, R, TBM, VX, K, NW, PER, FAST, LATE, YL>(), &occ_of<TS, R, TBM, VX, K, NW, PER, FAST, LATE, YL>}
+#define S3D_ENTRY(TS, R, TBM, VX, K, NW, PER, FAST, LATE, YL, FLX)                                        \
+    Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, R, TBM, VX, K, NW, FAST, LATE, YL, FLX},    \
+           &launch<TS, R, TBM, VX, K, NW, PER, FAST, LATE, YL, FLX>,                                                 \
+           lds_of<TS, R, TBM, VX, K, NW, PER, FAST, LATE, YL, FLX>(), &occ_of<TS, R, TBM, VX, K, NW, PER, FAST, LATE, YL, FLX>}
 #define S3D_BCLY(TS, R, TBM, VX, K, NW, LATE, YL)                                                      \
-    S3D_ENTRY(TS, R, TBM, VX, K, NW, false, true, LATE, YL), S3D_ENTRY(TS, R, TBM, VX, K, NW, true, true, LATE, YL), \
-        S3D_ENTRY(TS, R, TBM, VX, K, NW, false, false, LATE, YL),                                      \
-        S3D_ENTRY(TS, R, TBM, VX, K, NW, true, false, LATE, YL)
+    S3D_ENTRY(TS, R, TBM, VX, K, NW, false, true, LATE, YL, false),                                    \
+        S3D_ENTRY(TS, R, TBM, VX, K, NW, true, true, LATE, YL, false),                                 \
+        S3D_ENTRY(TS, R, TBM, VX, K, NW, false, false, LATE, YL, false),                               \
+        S3D_ENTRY(TS, R, TBM, VX, K, NW, true, false, LATE, YL, false)
 #define S3D_BCL(TS, R, TBM, VX, K, NW, LATE) S3D_BCLY(TS, R, TBM, VX, K, NW, LATE, false)
 #define S3D_BC(TS, R, TBM, VX, K, NW) S3D_BCL(TS, R, TBM, VX, K, NW, false)
 #define S3D_BCY(TS, R, TBM, VX, K, NW, LATE) S3D_BCLY(TS, R, TBM, VX, K, NW, LATE, true)
+// outflow-summing variants: zero rule only (the periodic grid has no boundary)
+#define S3D_FLUX(TS, R, TBM, VX, K, NW, LATE, YL)                                                      \
+    S3D_ENTRY(TS, R, TBM, VX, K, NW, false, true, LATE, YL, true),                                     \
+        S3D_ENTRY(TS, R, TBM, VX, K, NW, false, false, LATE, YL, true)
 
 }  // namespace s3d
 }  // namespace st
