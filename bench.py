@@ -154,7 +154,7 @@ class Workload:
     """A plan, its device buffers and the figures needed for the report."""
 
 
-def heat3d(torch, st, synth, dtype, select=None, n=512, steps=100, alpha=0.15):
+def heat3d(torch, st, synth, dtype, select=None, n=512, steps=100, alpha=0.15, flux=False):
     w = Workload()
     shape = (n, n, n)
     wdt = "f64" if dtype == "f64" else "f32"
@@ -171,8 +171,24 @@ def heat3d(torch, st, synth, dtype, select=None, n=512, steps=100, alpha=0.15):
     w.steps, w.cells, w.dtype = steps, n ** 3, dtype
     w.name = f"3D 7-point heat stencil, {n}^3, {steps} steps, alpha {alpha}, zero boundary"
     w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
+    if flux:
+        # the same sweep through stencil_run_flux: FP64 outflow of every step
+        w.flux = torch.zeros(1, dtype=torch.float64, device="cuda")
+        w.run = lambda: w.plan.run_flux(w.u, w.coeffs, w.steps, w.flux, work=w.work)
     w.kernel_tb = w.plan.info()["tb"]
     return w
+
+
+def flux_drift(torch, w):
+    """One run of an outflow workload from its initial field: relative gap
+    between the initial total and final total + outflow."""
+    s0 = float(w.u.double().sum())
+    w.flux.zero_()
+    w.run()
+    torch.cuda.synchronize()
+    sT = float(w.u.double().sum())
+    out = float(w.flux.cpu()[0])
+    return (s0 - sT - out) / s0, out / s0
 
 
 def heat2d(torch, st, synth, dtype, select=None, n=512, steps=100, alpha=0.2):
@@ -310,6 +326,8 @@ def main():
     ap.add_argument("--variant", type=int, default=-1, help="force a tiling candidate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--flux", action="store_true",
+                    help="heat3d through stencil_run_flux (FP64 outflow of every step)")
     ap.add_argument("--cpu-steps", type=int, default=30, help="oracle steps in the CPU sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 512^3 FP64 device copy instead (bandwidth reference)")
@@ -344,7 +362,12 @@ def main():
         return
 
     dtype = args.dtype or DEFAULT_DTYPE[args.workload]
-    w = WORKLOADS[args.workload](torch, st, synth, dtype, _select(args))
+    if args.flux:
+        if args.workload != "heat3d":
+            sys.exit("--flux applies to the heat3d workload")
+        w = heat3d(torch, st, synth, dtype, _select(args), flux=True)
+    else:
+        w = WORKLOADS[args.workload](torch, st, synth, dtype, _select(args))
     info = w.plan.info()
     log(f"plan: {info}")
     tkey = [args.workload, dtype, info["kernel"], info["tb"], info["tile_x"], info["tile_y"], info["tile_z"],
@@ -397,6 +420,15 @@ def main():
             sec["f32_fused_depth"] = w32.kernel_tb
             del w32
             torch.cuda.empty_cache()
+            for fdt in ("f64", "f32"):
+                wf = heat3d(torch, st, synth, fdt, flux=True)
+                drift, frac = flux_drift(torch, wf)
+                _, vf, _, _, _ = measure(torch, wf, max(3, args.steps // 2), 1)
+                sec[f"{fdt}_with_outflow_gcells"] = round(vf, 3)
+                sec[f"{fdt}_outflow_total_drift"] = float(f"{drift:.3e}")
+                sec[f"{fdt}_outflow_fraction_of_total"] = round(frac, 6)
+                del wf
+                torch.cuda.empty_cache()
             wb = batch(torch, st, synth, "f32")
             _, vb, _, _, _ = measure(torch, wb, 2, 1)
             sec["batch64_f32_gcells"] = round(vb, 3)

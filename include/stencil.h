@@ -172,7 +172,9 @@ st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs
  * to rounding and tracks the drift of long FP32 / bfloat16 runs.
  *   flux    device pointer to ONE double; the outflow of the `steps` steps
  *           (each step's sum over the state it reads, weights rounded to the
- *           compute precision, products and sums in FP64) is ADDED to it.
+ *           compute precision, products and sums in FP64 -- except that the
+ *           fused FP32-compute kernels add the up to 4 rows of one x-face
+ *           column that a lane holds in FP32 first) is ADDED to it.
  *           Under the periodic rule nothing leaves and *flux is not touched.
  *   other arguments as for stencil_run; the grid ends bit-identical to
  *           stencil_run's.

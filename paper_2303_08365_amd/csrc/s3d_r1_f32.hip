@@ -10,7 +10,7 @@ static const Entry3 kTable[] = {
     S3D_BCL(float, 1, 3, 4, 4, 8, true), S3D_BCL(float, 1, 4, 4, 3, 8, true),
     S3D_BCY(float, 1, 2, 4, 4, 8, false), S3D_BCY(float, 1, 3, 4, 4, 8, true),
     S3D_BCY(float, 1, 3, 4, 5, 8, true), S3D_BCY(float, 1, 4, 4, 4, 8, true),
-    S3D_FLUX(float, 1, 4, 4, 4, 8, true, true),
+    S3D_FLUX(float, 1, 4, 4, 4, 8, true, true), S3D_FLUX(float, 1, 4, 4, 3, 8, true, false),
 };
 }  // namespace s3d
 

@@ -100,7 +100,10 @@ struct Kern {
         int lane, wave;
         TC w[NP];
         double* fpart;                 // FLX: this wave's partial outflow slot
-        bool fedge;                    // FLX: the output tile is within R of an x or y face
+        bool fx;                       // FLX: the output tile is within R of an x face
+        bool fy;                       // FLX: this wave's owned rows reach within R of a y face
+        bool fzy;                      // FLX: fy, or the z chunk reaches within R of a z face
+        TC rw[K];                      // FLX: 1 for the wave's owned rows, 0 for the others
     };
 
     static __device__ __forceinline__ bool ghost(int32_t i, int32_t n) {
@@ -360,40 +363,85 @@ struct Kern {
         }
         return s;
     }
-    // Adds the outflow of the wave's owned cells of plane z of one state.
-    static __device__ __forceinline__ void flux_add(const Ctx& c, double& fl, int32_t z, const TC (&v)[K][VX]) {
-        if (static_cast<uint32_t>(z - c.zs) >= static_cast<uint32_t>(c.ze - c.zs)) return;
-        const double cz = leave_w(c, z, c.nz, 1, 1 + 5 * R);
-        if (!c.fedge && cz == 0.0) return;
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int32_t y = c.yw + k;
-            if (static_cast<uint32_t>(y - c.oy0) >= static_cast<uint32_t>(c.oy1 - c.oy0)) continue;
-            const double czy = cz + leave_w(c, y, c.ny, 1 + R, 1 + 4 * R);
-#pragma unroll
-            for (int e = 0; e < VX; ++e) {
-                const int32_t x = c.xl + e;
-                const bool own = static_cast<uint32_t>(x - c.ox0) < static_cast<uint32_t>(c.ox1 - c.ox0);
-                const double cc = czy + leave_w(c, x, c.nx, 1 + 2 * R, 1 + 3 * R);
-                acc = own ? fma(static_cast<double>(v[k][e]), cc, acc) : acc;
-            }
-        }
-        fl += acc;
-    }
-    static __device__ __forceinline__ void flux_store(const Ctx& c, double fl) {
-        const double t = wave_sum(fl);
-        if (c.lane == 0) *c.fpart = t;
-    }
-
     template <int TB>
     struct State {
         TC q[TB][Q][K][VX];
         TC pf[LATE ? 1 : P][K][VX];  // unused when LATE
         TC rpf[PR][RROWS][VX];
         TC xpf[PR];
-        double fl;                   // FLX: outflow of this wave's owned cells so far
+        double fl;                   // FLX: outflow of this wave's owned cells so far (z and y parts)
+        double xa[(FAST && R == 1) ? 2 : VX];  // FLX: owned-row sums of the candidate face columns
     };
+
+    // Adds the outflow of the wave's owned cells of plane z of one state:
+    // sum over cells of u * (cz + cy + cx).
+    //   * z and y parts (nonzero on the band planes, and on the band rows of
+    //     the one or two waves per edge tile that own them): FP64 per cell,
+    //     behind wave-uniform branches;
+    //   * x part (every plane of the x-edge tiles): per candidate column, the
+    //     sum over the owned rows of the plane (K values, in the compute
+    //     precision) is added to an FP64 per-lane column total; the totals
+    //     are weighted once, when the wave stores its partial sum.  With
+    //     radius 1 in the whole-vector layout a face column is the first
+    //     column of lane 0 or the last of lane 63 (edge tiles move inward to
+    //     touch the faces, and only they own a face column), so only those
+    //     two columns are candidates.
+    static constexpr bool XEDGE2 = FAST && R == 1;
+    static constexpr int NXB = XEDGE2 ? 2 : VX;
+    static __device__ __forceinline__ int xcol(int i) { return XEDGE2 ? (i == 0 ? 0 : VX - 1) : i; }
+    template <int TB>
+    static __device__ __forceinline__ void flux_add(const Ctx& c, State<TB>& s, int32_t z, const TC (&v)[K][VX]) {
+        if (static_cast<uint32_t>(z - c.zs) >= static_cast<uint32_t>(c.ze - c.zs)) return;
+        if (c.fzy) {
+            const bool zb = z < R || z >= c.nz - R;
+            if (zb || c.fy) {
+                const double cz = zb ? leave_w(c, z, c.nz, 1, 1 + 5 * R) : 0.0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int32_t y = c.yw + k;
+                    if (static_cast<uint32_t>(y - c.oy0) >= static_cast<uint32_t>(c.oy1 - c.oy0)) continue;
+                    const bool yb = y < R || y >= c.ny - R;
+                    if (!zb && !yb) continue;
+                    const double czy = yb ? cz + leave_w(c, y, c.ny, 1 + R, 1 + 4 * R) : cz;
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) {
+                        const bool own =
+                            static_cast<uint32_t>(c.xl + e - c.ox0) < static_cast<uint32_t>(c.ox1 - c.ox0);
+                        // opaque copy: keeps the conversion inside this rare
+                        // branch (otherwise it is hoisted into every plane)
+                        TC u = v[k][e];
+                        __asm__ volatile("" : "+v"(u));
+                        s.fl = own ? fma(static_cast<double>(u), czy, s.fl) : s.fl;
+                    }
+                }
+            }
+        }
+        if (c.fx) {
+#pragma unroll
+            for (int i = 0; i < NXB; ++i) {
+                TC col = c.rw[0] * v[0][xcol(i)];
+#pragma unroll
+                for (int k = 1; k < K; ++k) col = fma_c(c.rw[k], v[k][xcol(i)], col);
+                s.xa[i] += static_cast<double>(col);
+            }
+        }
+    }
+    template <int TB>
+    static __device__ __forceinline__ void flux_store(const Ctx& c, const State<TB>& s) {
+        double t = s.fl;
+#pragma unroll
+        for (int i = 0; i < NXB; ++i) {
+            const int32_t x = c.xl + xcol(i);
+            const bool own = static_cast<uint32_t>(x - c.ox0) < static_cast<uint32_t>(c.ox1 - c.ox0);
+            t = fma(s.xa[i], own ? leave_w(c, x, c.nx, 1 + 2 * R, 1 + 3 * R) : 0.0, t);
+        }
+        flux_store_sum(c, t);
+    }
+    static __device__ __forceinline__ void flux_store_sum(const Ctx& c, double fl) {
+        const double t = wave_sum(fl);
+        if (c.lane == 0) *c.fpart = t;
+    }
+
 
     template <int TB, int J>
     static __device__ __forceinline__ void step(const Ctx& c, int32_t it, int32_t zfirst, State<TB>& s, TC* lds) {
@@ -413,7 +461,7 @@ struct Kern {
             load_main(c, zin + P, s.pf[SM]);
             load_ring(c, zin + PR - R, s.rpf[SR], s.xpf[SR]);
         }
-        if constexpr (FLX) flux_add(c, s.fl, zin, s.q[0][J]);  // the pass's input state
+        if constexpr (FLX) flux_add(c, s, zin, s.q[0][J]);  // the pass's input state
 
         constexpr int CEN = (J - R + Q) % Q;
 #pragma unroll
@@ -471,7 +519,7 @@ struct Kern {
                     store_plane(c, zc, out);
                 } else {
                     finish(c, zc, out);
-                    if constexpr (FLX) flux_add(c, s.fl, zc, out);  // state after step l
+                    if constexpr (FLX) flux_add(c, s, zc, out);  // state after step l
 #pragma unroll
                     for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -491,7 +539,6 @@ struct Kern {
                                                 State<TB>& s, TC* lds, std::integer_sequence<int, J...>) {
         ((base + J < nit ? step<TB, J>(c, base + J, zfirst, s, lds) : void()), ...);
     }
-
     static __device__ __forceinline__ void run(const Stream3DArgs& a, TC* lds) {
         Ctx c;
         c.lane = threadIdx.x & 63;
@@ -501,7 +548,7 @@ struct Kern {
         const uint32_t item = static_cast<uint32_t>(xcd_remap(blockIdx.x, gridDim.x));
         if constexpr (FLX) c.fpart = a.flux_part + static_cast<int64_t>(blockIdx.x) * NW + c.wave;
         if (item >= tiles) {
-            if constexpr (FLX) flux_store(c, 0.0);
+            if constexpr (FLX) flux_store_sum(c, 0.0);
             return;
         }
         const uint32_t txy = item / static_cast<uint32_t>(a.tiles_x);
@@ -568,9 +615,20 @@ struct Kern {
         c.out_bytes = static_cast<uint32_t>(c.ox1 - c.ox0) * sizeof(TS);
         c.zs = cz * a.chunk_z;
         c.ze = c.zs + a.chunk_z < c.nz ? c.zs + a.chunk_z : c.nz;
-        c.fedge = c.ox0 < R || c.ox1 > c.nx - R || c.oy0 < R || c.oy1 > c.ny - R;
 #pragma unroll
         for (int p = 0; p < NP; ++p) c.w[p] = static_cast<TC>(a.w[p]);
+        if constexpr (FLX) {
+            c.fx = c.ox0 < R || c.ox1 > c.nx - R;
+            c.fy = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int32_t y = c.yw + k;
+                const bool own = static_cast<uint32_t>(y - c.oy0) < static_cast<uint32_t>(c.oy1 - c.oy0);
+                c.fy = c.fy || (own && (y < R || y >= c.ny - R));
+                c.rw[k] = own ? TC(1) : TC(0);
+            }
+            c.fzy = c.fy || c.zs < R || c.ze > c.nz - R;
+        }
         // one specialised pipeline per fused depth: no run-time level tests
         // inside the loop
         const int tb = a.tb;
@@ -600,6 +658,8 @@ struct Kern {
         State<TB> s;
         s.fl = 0.0;
 #pragma unroll
+        for (int i = 0; i < NXB; ++i) s.xa[i] = 0.0;
+#pragma unroll
         for (int l = 0; l < TB; ++l)
 #pragma unroll
             for (int sl = 0; sl < Q; ++sl)
@@ -620,7 +680,7 @@ struct Kern {
         int32_t base = 0;
         for (; base + Q <= nit; base += Q) group<TB>(c, base, zfirst, s, lds, std::make_integer_sequence<int, Q>{});
         tail<TB>(c, base, nit, zfirst, s, lds, std::make_integer_sequence<int, Q>{});
-        if constexpr (FLX) flux_store(c, s.fl);
+        if constexpr (FLX) flux_store(c, s);
     }
 };
 

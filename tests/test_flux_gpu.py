@@ -83,7 +83,11 @@ def test_3d_fused_and_one_step_outflow_agree(dtype):
     plan.select(kernel=0)
     g2, f2 = _run_flux(plan, u0, w, 10, dtype)
     assert np.array_equal(g1, g2)
-    assert abs(f1 - f2) <= 1e-13 * abs(f2), (f1, f2)
+    # FP64: the same products, summed in another order.  FP32 compute: the
+    # fused kernels first add up to K = 4 rows of an x-face column in FP32
+    # (relative error at most 3 * 2^-24 of that part, all values >= 0 here)
+    tol = 1e-13 if dtype == "f64" else 3 * 2.0 ** -24
+    assert abs(f1 - f2) <= tol * abs(f2), (f1, f2)
 
 
 @pytest.mark.parametrize("dtype,kind,r,shape", [
