@@ -52,10 +52,12 @@ struct Stream2DArgs {
     Stream2DGrid one;           // used when grids == nullptr
     int32_t ngrids;
     int64_t items;              // total (grid, strip, chunk) work items
+    double* flux_part;          // outflow variants (single grid): one partial sum per work item
 };
 // Instantiation key for the 2D family.
 struct Stream2DKey {
     int32_t dtype, bc, cls, radius, tbmax, vx;
+    int32_t flux;  // also sums the outflow of every step of the pass (zero rule, single grid)
 };
 hipError_t launch_stream2d(const Stream2DKey& k, const Stream2DArgs& a, hipStream_t s);
 bool stream2d_has(const Stream2DKey& k);

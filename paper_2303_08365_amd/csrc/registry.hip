@@ -10,7 +10,7 @@ const Entry2* find2(const Stream2DKey& k) {
         for (int i = 0; i < t.n; ++i) {
             const Stream2DKey& e = t.e[i].key;
             if (e.dtype == k.dtype && e.bc == k.bc && e.cls == k.cls && e.radius == k.radius &&
-                e.tbmax == k.tbmax && e.vx == k.vx)
+                e.tbmax == k.tbmax && e.vx == k.vx && e.flux == k.flux)
                 return &t.e[i];
         }
     return nullptr;

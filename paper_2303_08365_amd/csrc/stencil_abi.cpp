@@ -557,7 +557,13 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
         G.tb = tb;
         G.tile_begin = 0;
         for (int i = 0; i < p->npoints; ++i) G.w[i] = wcan[i];
-        e = launch_stream2d(c.k2, a, s);
+        Stream2DKey key = c.k2;
+        if (fpart) {
+            key.flux = 1;
+            if (!stream2d_has(key)) key.tbmax = 8;  // the deepest twin runs any depth
+            a.flux_part = fpart;
+        }
+        e = launch_stream2d(key, a, s);
         if (e != hipSuccess) return hip_fail(e, "stream2d launch");
         return ST_OK;
     }
@@ -605,7 +611,15 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
 // before the step reads it.  Either way a one-work-group kernel then adds the
 // pass's partial sums to the FP64 accumulator in a fixed order.
 bool flux_fused(const st_plan_s* p, const Candidate& c) {
-    if (c.kernel != ST_KERNEL_STREAM3D || p->bc != kZero) return false;
+    if (p->bc != kZero) return false;
+    if (c.kernel == ST_KERNEL_STREAM2D) {
+        Stream2DKey k = c.k2;
+        k.flux = 1;
+        if (stream2d_has(k)) return true;
+        k.tbmax = 8;
+        return c.tb <= 8 && stream2d_has(k);
+    }
+    if (c.kernel != ST_KERNEL_STREAM3D) return false;
     Stream3DKey k = c.k3;
     k.flux = 1;
     k.fast = 1;
@@ -617,6 +631,11 @@ bool flux_fused(const st_plan_s* p, const Candidate& c) {
 // Partial sums one pass of depth tb writes (-1: tiling infeasible).
 int64_t flux_parts(const st_plan_s* p, const Candidate& c, bool fused, int tb) {
     if (!fused) return kFluxBandBlocks;
+    if (c.kernel == ST_KERNEL_STREAM2D) {
+        Geo2 g2;
+        if (!geo2(c, p->n[1], p->n[2], tb, g2)) return -1;
+        return g2.items;
+    }
     Geo3 g;
     if (!geo3(c, p->n, tb, g)) return -1;
     return static_cast<int64_t>(g.tiles_x) * g.tiles_y * g.chunks_z * c.k3.nw;
@@ -659,7 +678,7 @@ st_status run_steps(st_plan_s* p, const Candidate& c_in, void* grid, void* work,
         int64_t need = 0;
         for (int t : passes) {
             const int64_t n = flux_parts(p, c, fused, t);
-            if (n < 0) return fail(ST_ERR_UNSUPPORTED, "3D tiling infeasible");
+            if (n < 0) return fail(ST_ERR_UNSUPPORTED, "tiling infeasible");
             need = std::max(need, n);
         }
         if (st_status r = ensure_flux_parts(p, need, s); r != ST_OK) return r;

@@ -47,7 +47,7 @@ namespace st {
 
 namespace s2d {
 
-template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER>
+template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER, bool FLX>
 struct Kern {
     using S = Storage<TS>;
     using TC = typename S::TC;
@@ -74,6 +74,9 @@ struct Kern {
         uint32_t so, out_bytes; // store: lane offset from ofirst, output row bytes
         int lane;
         TC w[NP];
+        double* fpart;          // FLX: this wave's partial outflow slot
+        bool fx;                // FLX: the strip owns a column within R of an x face
+        bool fyb;               // FLX: the chunk owns a row within R of a y face
     };
 
     static __device__ __forceinline__ bool ghost(int32_t i, int32_t n) {
@@ -271,7 +274,70 @@ struct Kern {
         TC pf[Q][VX];
         TC pfx[Q];
         int32_t yl;         // next row to load (wrapped when periodic)
+        double fl;          // FLX: outflow through the y faces so far
+        double xa[2];       // FLX: totals of the two candidate x-face columns
     };
+
+    // Outflow (FLX: radius-1 star, zero rule, whole-vector rows).  The state
+    // a step reads sends w_p * u(c) to c - off_p; a cell's leaving weight is
+    // cy(y) + cx(x).  Canonical indices: y -1 is point 1, x -1 point 2, x +1
+    // point 3, y +1 point 4; a point -1 along an axis sends to i + 1, a point
+    // +1 to i - 1.  The y part is nonzero only on the first and last row (the
+    // first and last y chunk), summed per cell in FP64 behind wave-uniform
+    // branches; the x part only in column 0 (lane 0's first column: the
+    // strip touching the face moves inward to start there) and column nx - 1
+    // (lane 63's last), whose per-lane FP64 totals are weighted once at the
+    // end.
+    static_assert(!FLX || (R == 1 && CLS == kStar && !PER), "outflow variants: radius-1 star, zero rule");
+    static __device__ __forceinline__ double leave_y(const Ctx& c, int32_t y) {
+        return (y + 1 >= c.ny ? static_cast<double>(c.w[1]) : 0.0) + (y - 1 < 0 ? static_cast<double>(c.w[4]) : 0.0);
+    }
+    static __device__ __forceinline__ double leave_x(const Ctx& c, int32_t x) {
+        return (x + 1 >= c.nx ? static_cast<double>(c.w[2]) : 0.0) + (x - 1 < 0 ? static_cast<double>(c.w[3]) : 0.0);
+    }
+    template <int TB, bool FAST>
+    static __device__ __forceinline__ void flux_add(const Ctx& c, State<TB>& s, int32_t y, const TC (&v)[VX]) {
+        if (static_cast<uint32_t>(y - c.ys) >= static_cast<uint32_t>(c.ye - c.ys)) return;
+        if (c.fyb && (y < 1 || y >= c.ny - 1)) {
+            const double cy = leave_y(c, y);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const bool own = static_cast<uint32_t>(c.xl + e - c.ofirst) < static_cast<uint32_t>(c.olast - c.ofirst);
+                // opaque copy: keeps the conversion inside this rare branch
+                TC u = v[e];
+                __asm__ volatile("" : "+v"(u));
+                s.fl = own ? fma(static_cast<double>(u), cy, s.fl) : s.fl;
+            }
+        }
+        if (c.fx) {
+            if constexpr (FAST) {
+                s.xa[0] += static_cast<double>(v[0]);
+                s.xa[1] += static_cast<double>(v[VX - 1]);
+            } else {
+                // element-wise rows (narrow or unaligned grids): any column
+#pragma unroll
+                for (int e = 0; e < VX; ++e) {
+                    const int32_t x = c.xl + e;
+                    const bool own = static_cast<uint32_t>(x - c.ofirst) < static_cast<uint32_t>(c.olast - c.ofirst);
+                    s.fl = own ? fma(static_cast<double>(v[e]), leave_x(c, x), s.fl) : s.fl;
+                }
+            }
+        }
+    }
+    template <int TB, bool FAST>
+    static __device__ __forceinline__ void flux_store(const Ctx& c, const State<TB>& s) {
+        double t = s.fl;
+        if constexpr (FAST) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int32_t x = c.xl + (i == 0 ? 0 : VX - 1);
+                const bool own = static_cast<uint32_t>(x - c.ofirst) < static_cast<uint32_t>(c.olast - c.ofirst);
+                t = fma(s.xa[i], own ? leave_x(c, x) : 0.0, t);
+            }
+        }
+        t = wave_sum(t);
+        if (c.lane == 0) *c.fpart = t;
+    }
 
     static __device__ __forceinline__ int32_t next_row(const Ctx& c, int32_t y) {
         if constexpr (PER) return y + 1 == c.ny ? 0 : y + 1;
@@ -284,6 +350,7 @@ struct Kern {
 #pragma unroll
         for (int e = 0; e < VX; ++e) s.q[0][J][e] = s.pf[J][e];
         s.xq[J] = s.pfx[J];
+        if constexpr (FLX) flux_add<TB, FAST>(c, s, yin, s.q[0][J]);  // the pass's input state
         // rows past the end of the stream are never consumed: load the last
         // streamed row again (a cache hit)
         load_row<FAST>(c, yin + Q <= c.ylast ? s.yl : c.ylast_w, s.pf[J], s.pfx[J]);
@@ -298,6 +365,7 @@ struct Kern {
                 store_row<FAST>(c, yc, out);
             } else {
                 finish<FAST>(c, yc, out);
+                if constexpr (FLX) flux_add<TB, FAST>(c, s, yc, out);  // state after step l
 #pragma unroll
                 for (int e = 0; e < VX; ++e) s.q[l + 1][J][e] = out[e];
             }
@@ -333,6 +401,8 @@ struct Kern {
 #pragma unroll
                 for (int e = 0; e < VX; ++e) s.q[l][sl][e] = TC(0);
         s.yl = wrap_row(c, yfirst);
+        s.fl = 0.0;
+        s.xa[0] = s.xa[1] = 0.0;
 #pragma unroll
         for (int sl = 0; sl < Q; ++sl) {
             s.xq[sl] = TC(0);
@@ -343,6 +413,7 @@ struct Kern {
         for (; base + Q <= nit; base += Q)
             group<TB, FAST>(c, base, yfirst, s, std::make_integer_sequence<int, Q>{});
         tail<TB, FAST>(c, base, nit, yfirst, s, std::make_integer_sequence<int, Q>{});
+        if constexpr (FLX) flux_store<TB, FAST>(c, s);
     }
 
     // one specialised pipeline per fused depth
@@ -413,27 +484,32 @@ struct Kern {
         c.ye = c.ys + chunk_y < c.ny ? c.ys + chunk_y : c.ny;
 #pragma unroll
         for (int p = 0; p < NP; ++p) c.w[p] = static_cast<TC>(uni(gp->w[p]));
+        if constexpr (FLX) {
+            c.fpart = a.flux_part + item;
+            c.fx = c.ofirst < 1 || c.olast > c.nx - 1;
+            c.fyb = c.ys < 1 || c.ye > c.ny - 1;
+        }
         if (fast) dispatch<true>(c, tb);
         else dispatch<false>(c, tb);
     }
 };
 
-template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER>
+template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER, bool FLX>
 __global__ __launch_bounds__(256) void stream2d_kernel(const Stream2DArgs a) {
-    Kern<TS, R, CLS, TBMAX, VX, PER>::run(a);
+    Kern<TS, R, CLS, TBMAX, VX, PER, FLX>::run(a);
 }
 
-template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER>
+template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER, bool FLX>
 void launch(const Stream2DArgs& a, hipStream_t s) {
     const int64_t wgs = (a.items + 3) / 4;
-    hipLaunchKernelGGL((stream2d_kernel<TS, R, CLS, TBMAX, VX, PER>), dim3(static_cast<unsigned>(wgs)),
+    hipLaunchKernelGGL((stream2d_kernel<TS, R, CLS, TBMAX, VX, PER, FLX>), dim3(static_cast<unsigned>(wgs)),
                        dim3(256), 0, s, a);
 }
 
-template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER>
+template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER, bool FLX>
 int occ_of() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_kernel<TS, R, CLS, TBMAX, VX, PER>, 256, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_kernel<TS, R, CLS, TBMAX, VX, PER, FLX>, 256, 0) !=
         hipSuccess)
         n = 0;
     return n;
@@ -444,11 +520,13 @@ template <> constexpr int32_t dtype_of<double>() { return kF64; }
 template <> constexpr int32_t dtype_of<float>() { return kF32; }
 template <> constexpr int32_t dtype_of<bf16s>() { return kBF16; }
 
-#define S2D_ENTRY(TS, R, CLS, TBM, VX, PER)                                                    \
-    Entry2{Stream2DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, CLS, R, TBM, VX},            \
-           &launch<TS, R, CLS, TBM, VX, PER>, &occ_of<TS, R, CLS, TBM, VX, PER>}
+#define S2D_ENTRY(TS, R, CLS, TBM, VX, PER, FLX)                                               \
+    Entry2{Stream2DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, CLS, R, TBM, VX, FLX},       \
+           &launch<TS, R, CLS, TBM, VX, PER, FLX>, &occ_of<TS, R, CLS, TBM, VX, PER, FLX>}
 #define S2D_BC(TS, R, CLS, TBM, VX) \
-    S2D_ENTRY(TS, R, CLS, TBM, VX, false), S2D_ENTRY(TS, R, CLS, TBM, VX, true)
+    S2D_ENTRY(TS, R, CLS, TBM, VX, false, false), S2D_ENTRY(TS, R, CLS, TBM, VX, true, false)
+// outflow-summing variant (radius-1 star, zero rule, single grid)
+#define S2D_FLUX(TS, TBM, VX) S2D_ENTRY(TS, 1, kStar, TBM, VX, false, true)
 
 }  // namespace s2d
 }  // namespace st

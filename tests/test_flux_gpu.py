@@ -69,13 +69,14 @@ def test_3d_heat_outflow_matches_oracle(dtype, shape):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
-def test_3d_fused_and_one_step_outflow_agree(dtype):
+@pytest.mark.parametrize("shape", [(24, 61, 530), (300, 1100), (45, 77)])
+def test_fused_and_one_step_outflow_agree(dtype, shape):
     # the fused twin sums inside its passes; the naive candidate runs one step
     # per pass with the band kernel: same states, sums in another order
     import paper_2303_08365_amd as st
-    offs = synth.star_offsets(3, 1)
-    w = synth.heat_weights(3, 0.15, "f64" if dtype == "f64" else "f32")
-    shape = (24, 61, 530)
+    nd = len(shape)
+    offs = synth.star_offsets(nd, 1)
+    w = synth.heat_weights(nd, 0.15 if nd == 3 else 0.2, "f64" if dtype == "f64" else "f32")
     u0 = synth.uniform_field(shape, seed=22)
     plan = st.Plan(offs, shape, dtype, "zero")
     print(f"flux fused/band {dtype} plan {plan.info()}", flush=True)
@@ -84,7 +85,7 @@ def test_3d_fused_and_one_step_outflow_agree(dtype):
     g2, f2 = _run_flux(plan, u0, w, 10, dtype)
     assert np.array_equal(g1, g2)
     # FP64: the same products, summed in another order.  FP32 compute: the
-    # fused kernels first add up to K = 4 rows of an x-face column in FP32
+    # fused 3D kernels first add up to K = 4 rows of an x-face column in FP32
     # (relative error at most 3 * 2^-24 of that part, all values >= 0 here)
     tol = 1e-13 if dtype == "f64" else 3 * 2.0 ** -24
     assert abs(f1 - f2) <= tol * abs(f2), (f1, f2)
