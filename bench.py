@@ -209,6 +209,29 @@ def heat2d(torch, st, synth, dtype, select=None, n=512, steps=100, alpha=0.2):
     return w
 
 
+def heat1d(torch, st, synth, dtype, select=None, n=10_000_000, steps=1000, alpha=0.25, radius=1):
+    """Tab. 1's Heat-1D (radius 1) / Star-1D5P (radius 2) shape: 10^7 cells;
+    1000 of its 10^5 steps; zero rule; U[0,1) seed 0."""
+    w = Workload()
+    shape = (n,)
+    wdt = "f64" if dtype == "f64" else "f32"
+    offs = synth.star_offsets(1, radius)
+    if radius == 1:
+        w.coeffs = list(synth.heat_weights(1, alpha, wdt))
+    else:
+        w.coeffs = list(synth.adjust_centre([0.0] + [alpha / (2 * radius)] * (2 * radius), wdt))
+    w.u = torch.from_numpy(synth.uniform_field(shape, seed=0)).to("cuda", _tdt(torch, dtype))
+    w.work = torch.empty_like(w.u)
+    w.plan = st.Plan(offs, shape, dtype, "zero", autotune=select is None)
+    if select:
+        w.plan.select(**select)
+    w.steps, w.cells, w.dtype = steps, n, dtype
+    w.name = f"1D {2 * radius + 1}-point star, {n} cells, {steps} steps, zero boundary"
+    w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
+    w.kernel_tb = w.plan.info()["tb"]
+    return w
+
+
 def box2d(torch, st, synth, dtype, select=None, n=8192, steps=1000):
     w = Workload()
     shape = (n, n)
@@ -301,9 +324,70 @@ def varcoef(torch, st, synth, dtype, select=None, n=256, steps=200, every=20, al
     return w
 
 
-WORKLOADS = {"varcoef": varcoef, "heat3d": heat3d, "heat2d": heat2d, "box2d": box2d, "star25": star25, "batch": batch}
-DEFAULT_DTYPE = {"varcoef": "f32", "heat3d": "f64", "heat2d": "f64", "box2d": "f32", "star25": "f32", "batch": "f32"}
-KERNEL_NAMES = {0: "naive_kernel", 1: "stream2d_kernel", 2: "stream3d_kernel", 3: "varcoef3d_kernel"}
+# Case study (paper Sec. 6.5): width of the initial Gaussian, in cells, chosen
+# so that the closed-form zero-rule solution has 52.0 at the centre after
+# 3.8e6 steps (derived from the oracle's spectral solution by
+# tests/golden/case_study_sigma.py, stored in tests/golden/case_study_gaussian.txt).
+CASE_SIGMA = None
+
+
+def case_study(torch, st, synth, steps, n=9600, mu=0.23, amplitude=100.0, sigma=None, chunk=50_000):
+    sigma = sigma or CASE_SIGMA
+    u0 = synth.gaussian_plate(n, sigma, amplitude)
+    c = n // 2 - 1
+    out = {"metric": "case study: Heat-2D 5-point, zero rule", "n": n, "mu": mu, "steps": steps,
+           "amplitude": amplitude, "sigma_cells": sigma, "initial_centre": float(u0[c, c])}
+    finals = {}
+    for dtype in ("f64", "f32"):
+        wdt = "f64" if dtype == "f64" else "f32"
+        coeffs = list(synth.heat_weights(2, mu, wdt))
+        plan = st.Plan(synth.star_offsets(2, 1), (n, n), dtype, "zero", autotune=True)
+        u = torch.from_numpy(u0).to("cuda", _tdt(torch, dtype))
+        work = torch.empty_like(u)
+        flux = torch.zeros(1, dtype=torch.float64, device="cuda")
+        total0 = float(u.double().sum())
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        gpu_s, done = 0.0, 0
+        while done < steps:
+            k = min(chunk, steps - done)
+            e0.record()
+            plan.run_flux(u, coeffs, k, flux, work=work)
+            e1.record()
+            torch.cuda.synchronize()
+            gpu_s += e0.elapsed_time(e1) / 1e3
+            done += k
+            log(f"case study {dtype}: {done} / {steps} steps, {n * n * done / gpu_s / 1e9:.1f} Gcell/s, "
+                f"centre {float(u[c, c]):.6f}")
+        finals[dtype] = u.double().cpu().numpy()
+        totalT, outflow = float(finals[dtype].sum()), float(flux.cpu()[0])
+        out[dtype] = {"gcells": round(n * n * steps / gpu_s / 1e9, 2), "gpu_seconds": round(gpu_s, 2),
+                      "centre": float(finals[dtype][c, c]), "plan": plan.info(),
+                      "outflow_fraction": round(outflow / total0, 6),
+                      "total_plus_outflow_drift": float(f"{(totalT + outflow - total0) / total0:.3e}")}
+        del u, work
+        torch.cuda.empty_cache()
+    # deviation of FP32 from FP64, in the form of the paper's Tab. 4
+    ref, d = finals["f64"], np.abs(finals["f32"] - finals["f64"])
+    rel = d / np.maximum(np.abs(ref), np.finfo(np.float64).tiny)
+    out["f32_vs_f64_percent_of_cells"] = {
+        "abs_gt_0.1": round(100.0 * float(np.mean(d > 0.1)), 2),
+        "abs_gt_0.5": round(100.0 * float(np.mean(d > 0.5)), 2),
+        "abs_gt_1.0": round(100.0 * float(np.mean(d > 1.0)), 2),
+        "rel_gt_1pct": round(100.0 * float(np.mean(rel > 0.01)), 2),
+        "rel_gt_3pct": round(100.0 * float(np.mean(rel > 0.03)), 2),
+        "rel_gt_5pct": round(100.0 * float(np.mean(rel > 0.05)), 2),
+        "max_abs": float(d.max()),
+    }
+    return out
+
+
+WORKLOADS = {"varcoef": varcoef, "heat3d": heat3d, "heat2d": heat2d, "box2d": box2d, "star25": star25, "batch": batch,
+             "heat1d": heat1d, "star1d5": lambda *a, **k: heat1d(*a, radius=2, **k)}
+DEFAULT_DTYPE = {"varcoef": "f32", "heat3d": "f64", "heat2d": "f64", "box2d": "f32", "star25": "f32", "batch": "f32",
+                 "heat1d": "f64", "star1d5": "f64"}
+KERNEL_NAMES = {0: "naive_kernel", 1: "stream2d_kernel", 2: "stream3d_kernel", 3: "varcoef3d_kernel",
+                4: "stream1d_kernel"}
 
 
 def measure(torch, w, steps, warmup):
@@ -329,6 +413,10 @@ def main():
     ap.add_argument("--flux", action="store_true",
                     help="heat3d through stencil_run_flux (FP64 outflow of every step)")
     ap.add_argument("--cpu-steps", type=int, default=30, help="oracle steps in the CPU sample")
+    ap.add_argument("--case-study", action="store_true",
+                    help="the paper's thermal-diffusion case study (Heat-2D 9600^2, CFL 0.23, 3.8e6 steps, "
+                         "Gaussian plate) in FP64 and FP32, with the FP32-vs-FP64 deviation table")
+    ap.add_argument("--case-steps", type=int, default=3_800_000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 512^3 FP64 device copy instead (bandwidth reference)")
     ap.add_argument("--ingest-counters", default=None, metavar="DIR",
@@ -348,6 +436,10 @@ def main():
     torch.cuda.init()
     dev = torch.cuda.get_device_properties(0)
     log(f"device: {dev.name} ({getattr(dev, 'gcnArchName', '?')}), CUs {dev.multi_processor_count}")
+
+    if args.case_study:
+        print(json.dumps(case_study(torch, st, synth, args.case_steps)), flush=True)
+        return
 
     if args.copy_probe:
         # plain device copy of one 512^3 FP64 grid: the achievable-bandwidth

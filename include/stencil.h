@@ -85,6 +85,7 @@ typedef struct st_plan_s* st_plan;
 #define ST_KERNEL_STREAM2D 1   /* 2D star/box, rows streamed through registers */
 #define ST_KERNEL_STREAM3D 2   /* 3D star, planes streamed, LDS row exchange   */
 #define ST_KERNEL_VARCOEF3D 3  /* 3D variable-coefficient heat                 */
+#define ST_KERNEL_STREAM1D 4   /* 1D star, a wave's strip of cells in registers */
 
 typedef struct {
     int32_t kernel;           /* ST_KERNEL_*                                    */

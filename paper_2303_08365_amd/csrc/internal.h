@@ -91,6 +91,24 @@ int stream3d_lds_bytes(const Stream3DKey& k);
 int stream3d_occupancy(const Stream3DKey& k);  // work-groups per CU, 0 if unknown
 
 // ----------------------------------------------------------------------------
+// 1D stars: a wave holds a strip of 64*VX cells and takes T_b steps in VGPRs
+// ----------------------------------------------------------------------------
+constexpr int kStream1DVX = 16;
+struct Stream1DArgs {
+    const void* src;
+    void* dst;
+    int64_t n;
+    int64_t strips;      // strips of out_w owned cells
+    int32_t out_w;       // owned cells per strip = 64*VX - 2*halo
+    int32_t halo;        // stale cells at each end of a strip (>= R*tb, multiple of VX)
+    int32_t tb;          // steps this pass
+    int32_t vec_ok;      // whole-vector access (n % VX == 0, n >= 64*VX, 16-byte aligned)
+    double w[9];         // canonical-order weights (2R+1 used)
+};
+bool stream1d_has(int dtype, int radius);
+hipError_t launch_stream1d(int dtype, int radius, bool periodic, const Stream1DArgs& a, hipStream_t s);
+
+// ----------------------------------------------------------------------------
 // variable-coefficient 3D heat step (zero rule) and its adjoint
 // ----------------------------------------------------------------------------
 struct VarcoefArgs {

@@ -260,6 +260,23 @@ bool geo2(const Candidate& c, int64_t ny, int64_t nx, int tb, Geo2& g, int64_t c
     return true;
 }
 
+struct Geo1 {
+    int32_t halo, out_w;
+    int64_t strips;
+};
+
+// 1D strips: 64*VX cells per wave, a stale halo of R*tb cells (rounded up to
+// whole lanes) at each end; 32-bit byte offsets (grid below 2 GiB).
+bool geo1(const st_plan_s* p, int tb, Geo1& g) {
+    const int64_t n = p->n[2];
+    if (n * elem_bytes(p->dtype) >= (int64_t(1) << 31)) return false;
+    g.halo = static_cast<int32_t>(round_up(static_cast<int64_t>(p->radius) * tb, kStream1DVX));
+    g.out_w = 64 * kStream1DVX - 2 * g.halo;
+    if (g.out_w < kStream1DVX) return false;
+    g.strips = ceil_div(n, g.out_w);
+    return true;
+}
+
 struct Geo3 {
     int32_t hxa, hya, out_w, out_h, tiles_x, tiles_y, chunk_z, chunks_z;
 };
@@ -393,6 +410,17 @@ void build_candidates(st_plan_s* p) {
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
             return (a.tb == want && a.chunk == 0) > (b.tb == want && b.chunk == 0);
         });
+    }
+    if (!force_naive && p->ndim == 1 && p->cls == kStar && stream1d_has(p->dtype, p->radius)) {
+        // the whole space-time tile in registers: any depth; deeper passes
+        // trade halo recomputation (2*R*tb of 1024 cells) for HBM passes
+        for (int tb : {32, 1, 2, 4, 8, 16, 64, 128}) {
+            Candidate c;
+            c.kernel = ST_KERNEL_STREAM1D;
+            c.tb = tb;
+            Geo1 g;
+            if (geo1(p, tb, g)) fast.push_back(c);
+        }
     }
     // STENCIL_CHUNK: fixed chunk length along the streamed axis (tuning)
     if (const char* ch = std::getenv("STENCIL_CHUNK")) {
@@ -535,6 +563,24 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
         if (e != hipSuccess) return hip_fail(e, "naive launch");
         return ST_OK;
     }
+    if (c.kernel == ST_KERNEL_STREAM1D) {
+        Geo1 g;
+        if (!geo1(p, tb, g)) return fail(ST_ERR_UNSUPPORTED, "1D tiling infeasible");
+        Stream1DArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.src = src;
+        a.dst = dst;
+        a.n = p->n[2];
+        a.strips = g.strips;
+        a.out_w = g.out_w;
+        a.halo = g.halo;
+        a.tb = tb;
+        a.vec_ok = vec_ok && p->n[2] >= 64 * kStream1DVX ? 1 : 0;
+        for (int i = 0; i < p->npoints; ++i) a.w[i] = wcan[i];
+        e = launch_stream1d(p->dtype, p->radius, p->bc == kPeriodic, a, s);
+        if (e != hipSuccess) return hip_fail(e, "stream1d launch");
+        return ST_OK;
+    }
     if (c.kernel == ST_KERNEL_STREAM2D) {
         Geo2 g;
         if (!geo2(c, p->n[1], p->n[2], tb, g)) return fail(ST_ERR_UNSUPPORTED, "2D tiling infeasible");
@@ -669,7 +715,10 @@ st_status run_steps(st_plan_s* p, const Candidate& c_in, void* grid, void* work,
     bool copy = false;
     const std::vector<int> passes = pass_list(steps, tb, copy);
     const size_t bytes = static_cast<size_t>(plan_cells(p)) * elem_bytes(p->dtype);
-    const int vx = c.kernel == ST_KERNEL_STREAM2D ? c.k2.vx : (c.kernel == ST_KERNEL_STREAM3D ? c.k3.vx : 1);
+    const int vx = c.kernel == ST_KERNEL_STREAM2D   ? c.k2.vx
+                   : c.kernel == ST_KERNEL_STREAM3D ? c.k3.vx
+                   : c.kernel == ST_KERNEL_STREAM1D ? kStream1DVX
+                                                    : 1;
     const bool vec_ok = (p->n[2] % vx == 0) && aligned16(grid) && aligned16(work);
     void* src = grid;
     void* dst = work;
@@ -731,6 +780,13 @@ void describe(const st_plan_s* p, const Candidate& c, int index, st_plan_info* i
         info->tile_z = 1;
         info->block = 256;
         info->workgroups = ceil_div(g.items, 4);
+    } else if (c.kernel == ST_KERNEL_STREAM1D) {
+        Geo1 g;
+        geo1(p, c.tb, g);
+        info->tile_x = g.out_w;
+        info->tile_y = info->tile_z = 1;
+        info->block = 256;
+        info->workgroups = ceil_div(g.strips, 4);
     } else if (c.kernel == ST_KERNEL_VARCOEF3D) {
         info->tile_x = info->tile_y = info->tile_z = 1;
         info->block = 256;

@@ -207,3 +207,29 @@ def test_streaming_copy_is_exact(nbytes):
     st.copy(dst, src)
     torch.cuda.synchronize()
     assert torch.equal(dst, src)
+
+
+# ---------------------------------------------------------------------------
+# 1D stars (Tab. 1 Heat-1D, Star-1D5P): every candidate, both rules, all types
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+@pytest.mark.parametrize("radius", [1, 2])
+@pytest.mark.parametrize("n", [37, 1000, 4096, 20011, 65536])
+def test_1d_star_all_candidates_match_oracle(dtype, bc, radius, n):
+    import paper_2303_08365_amd as st
+    offs = synth.star_offsets(1, radius)
+    w = _weights(offs, 5, dtype)
+    steps = 6 if dtype == "bf16" else 70
+    u0 = synth.uniform_field((n,), seed=6)
+    ref = oracle_ref(u0, offs, w, steps, bc, dtype)
+    plan = st.Plan(offs, (n,), dtype, bc)
+    results = []
+    for k, c in enumerate(plan.candidates()):
+        print(f"1d {dtype} {bc} r{radius} n {n} cand {k} kernel {c['kernel']} tb {c['tb']}", flush=True)
+        got, _ = gpu_sweep(u0, offs, w, steps, bc, dtype, select={"variant": k}, plan=plan)
+        check(got, ref, dtype, steps, f"cand {k}")
+        results.append(got)
+    assert plan.candidates()[0]["kernel"] == 4 or n < 64 * 16
+    for k, r in enumerate(results[1:], 1):
+        assert np.array_equal(r, results[0]), f"candidate {k} differs bitwise"
