@@ -49,7 +49,12 @@ def test_star_and_box_classification_and_families():
     assert p.info()["shape_class"] == 0 and p.info()["kernel"] == st.KERNEL_NAIVE
     p = st.Plan(synth.box_offsets(3, 1), (20, 20, 20), "f64")
     assert p.info()["shape_class"] == 2 and p.info()["kernel"] == st.KERNEL_NAIVE
+    # 1D stars of radius 1 and 2 run on the strip kernel; other 1D sets one step at a time
     p = st.Plan(synth.star_offsets(1, 2), (1000,), "f64")
+    assert p.info()["kernel"] == st.KERNEL_STREAM1D
+    p = st.Plan(synth.star_offsets(1, 3), (1000,), "f64")
+    assert p.info()["kernel"] == st.KERNEL_NAIVE
+    p = st.Plan([(0,), (2,)], (1000,), "f64")
     assert p.info()["kernel"] == st.KERNEL_NAIVE
     p = st.Plan(synth.star_offsets(3, 1), (64, 64, 64), "f64", naive=True)
     assert p.info()["kernel"] == st.KERNEL_NAIVE and p.info()["ncandidates"] == 1
