@@ -328,7 +328,7 @@ def varcoef(torch, st, synth, dtype, select=None, n=256, steps=200, every=20, al
 # so that the closed-form zero-rule solution has 52.0 at the centre after
 # 3.8e6 steps (derived from the oracle's spectral solution by
 # tests/golden/case_study_sigma.py, stored in tests/golden/case_study_gaussian.txt).
-CASE_SIGMA = None
+CASE_SIGMA = 1376.2
 
 
 def case_study(torch, st, synth, steps, n=9600, mu=0.23, amplitude=100.0, sigma=None, chunk=50_000):

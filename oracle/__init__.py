@@ -103,6 +103,27 @@ def sweep(u0: np.ndarray, offsets, weights, steps: int, bc="zero",
     return u
 
 
+def heat_spectral(u0: np.ndarray, alpha: float, steps: int) -> np.ndarray:
+    """Closed form of `steps` explicit heat steps (Eq. 3, increment form) under
+    the zero rule: the step is diagonal in the DST-I basis, with eigenvalue
+    1 - 4*alpha*sum_d sin^2(pi*k_d / (2*(n_d + 1))) for mode k; so transform,
+    raise the eigenvalues to the power `steps`, transform back.  scipy's
+    orthonormal DST-I is the library step.  Rounding differs from the loop
+    oracle (it is a different computation of the same exact result)."""
+    import scipy.fft
+    u0 = np.asarray(u0, dtype=np.float64)
+    lam = np.zeros(u0.shape)
+    for axis, n in enumerate(u0.shape):
+        k = np.arange(1, n + 1)
+        view = [1] * u0.ndim
+        view[axis] = n
+        lam = lam + (np.sin(np.pi * k / (2.0 * (n + 1))) ** 2).reshape(view)
+    lam = 1.0 - 4.0 * alpha * lam
+    c = scipy.fft.dstn(u0, type=1, norm="ortho")
+    c *= lam ** int(steps)
+    return scipy.fft.idstn(c, type=1, norm="ortho")
+
+
 def sweep_flux(u0: np.ndarray, offsets, weights, steps: int):
     """(u_T, outflow): the zero-rule sweep and the total amount its steps send
     across the grid's boundary (each step sends w_p * u[c] to c - off_p;

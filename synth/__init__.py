@@ -102,6 +102,15 @@ def round_to(a: np.ndarray, dtype: str) -> np.ndarray:
 # ----------------------------------------------------------------------------
 # stencil point lists
 # ----------------------------------------------------------------------------
+def gaussian_plate(n: int, sigma: float, amplitude: float = 100.0) -> np.ndarray:
+    """n x n field amplitude * exp(-r^2 / (2 sigma^2)), r measured from the
+    grid's centre point ((n-1)/2, (n-1)/2) in cells (the case study's initial
+    temperature: hottest at the centre, cooler towards the edges)."""
+    c = (n - 1) / 2.0
+    g = np.exp(-((np.arange(n) - c) ** 2) / (2.0 * sigma * sigma))
+    return amplitude * np.outer(g, g)
+
+
 def star_offsets(ndim: int, radius: int) -> List[Tuple[int, ...]]:
     """Centre plus 2*ndim*radius axis points.
 

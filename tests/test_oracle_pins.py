@@ -395,3 +395,25 @@ def test_outflow_zero_for_identity_and_zero_steps():
     assert out == 0.0
     _, out = oracle.sweep_flux(u, synth.star_offsets(2, 1), [0.6, 0.1, 0.1, 0.1, 0.1], 0)
     assert out == 0.0
+
+
+@pytest.mark.parametrize("shape,alpha,steps", [((9, 11), 0.23, 40), ((31,), 0.4, 17), ((6, 5, 7), 0.15, 9)])
+def test_heat_spectral_matches_loop_oracle(shape, alpha, steps):
+    # two computations of the same exact result: the DST-I closed form and the
+    # plain loop
+    u0 = synth.uniform_field(shape, seed=31)
+    assert oracle.rel_l2(oracle.heat_spectral(u0, alpha, steps), oracle.heat(u0, alpha, steps, bc="zero")) < 1e-13
+
+
+def test_heat_spectral_sin_mode_and_gaussian_symmetry():
+    n, alpha, steps = 40, 0.23, 300
+    x = (np.arange(n) + 1.0) / (n + 1.0)
+    mode = np.outer(np.sin(np.pi * x), np.sin(np.pi * x))
+    g = 1.0 - 4.0 * alpha * 2.0 * math.sin(math.pi / (2.0 * (n + 1))) ** 2
+    np.testing.assert_allclose(oracle.heat_spectral(mode, alpha, steps), g ** steps * mode, rtol=1e-12, atol=1e-15)
+    # a centred Gaussian stays symmetric and its four centre cells stay equal
+    u = oracle.heat_spectral(synth.gaussian_plate(n, 6.0), alpha, steps)
+    np.testing.assert_allclose(u, u[::-1, :], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(u, u.T, rtol=0, atol=1e-12)
+    c = n // 2 - 1
+    assert abs(u[c, c] - u[c + 1, c + 1]) < 1e-12 and u[c, c] == np.max(u)
