@@ -86,6 +86,7 @@ typedef struct st_plan_s* st_plan;
 #define ST_KERNEL_STREAM3D 2   /* 3D star, planes streamed, LDS row exchange   */
 #define ST_KERNEL_VARCOEF3D 3  /* 3D variable-coefficient heat                 */
 #define ST_KERNEL_STREAM1D 4   /* 1D star, a wave's strip of cells in registers */
+#define ST_KERNEL_BOX3D 5      /* 3D radius-1 box, planes streamed, one step     */
 
 typedef struct {
     int32_t kernel;           /* ST_KERNEL_*                                    */

@@ -19,7 +19,7 @@ __all__ = [
     "StencilError", "Plan", "BatchPlan", "run", "library", "library_path", "build",
     "F64", "F32", "BF16", "BC_ZERO", "BC_PERIODIC", "PLAN_AUTOTUNE", "PLAN_NAIVE",
     "PLAN_VARCOEF", "PLAN_GRAPH", "KERNEL_NAIVE", "KERNEL_STREAM2D", "KERNEL_STREAM3D", "KERNEL_VARCOEF3D",
-    "KERNEL_STREAM1D",
+    "KERNEL_STREAM1D", "KERNEL_BOX3D",
     "STATUS", "StencilFn", "varcoef_plan", "copy",
 ]
 
@@ -29,7 +29,7 @@ _LIB_PATH = os.path.join(_HERE, "libstencil.so")
 F64, F32, BF16 = 0, 1, 2
 BC_ZERO, BC_PERIODIC = 0, 1
 PLAN_AUTOTUNE, PLAN_NAIVE, PLAN_VARCOEF, PLAN_GRAPH = 0x1, 0x2, 0x4, 0x8
-KERNEL_NAIVE, KERNEL_STREAM2D, KERNEL_STREAM3D, KERNEL_VARCOEF3D, KERNEL_STREAM1D = 0, 1, 2, 3, 4
+KERNEL_NAIVE, KERNEL_STREAM2D, KERNEL_STREAM3D, KERNEL_VARCOEF3D, KERNEL_STREAM1D, KERNEL_BOX3D = 0, 1, 2, 3, 4, 5
 STATUS = {0: "ST_OK", -1: "ST_ERR_ARG", -2: "ST_ERR_UNSUPPORTED", -3: "ST_ERR_MISMATCH",
           -4: "ST_ERR_NOMEM", -5: "ST_ERR_HIP", -6: "ST_ERR_CAPTURE"}
 _DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}

@@ -109,6 +109,21 @@ bool stream1d_has(int dtype, int radius);
 hipError_t launch_stream1d(int dtype, int radius, bool periodic, const Stream1DArgs& a, hipStream_t s);
 
 // ----------------------------------------------------------------------------
+// 3D radius-1 boxes (27 points): one step per pass, planes streamed along z
+// ----------------------------------------------------------------------------
+constexpr int kBox3DK = 4;   // rows per wave
+constexpr int kBox3DNW = 4;  // waves per work-group
+struct Box3DArgs {
+    const void* src;
+    void* dst;
+    int64_t nz, ny, nx;
+    int32_t tiles_x, tiles_y, chunks_z, chunk_z;
+    double w[27];        // canonical-order weights
+};
+int box3d_vx(int dtype);  // columns per lane
+hipError_t launch_box3d(int dtype, bool periodic, bool fast, const Box3DArgs& a, hipStream_t s);
+
+// ----------------------------------------------------------------------------
 // variable-coefficient 3D heat step (zero rule) and its adjoint
 // ----------------------------------------------------------------------------
 struct VarcoefArgs {

@@ -277,6 +277,27 @@ bool geo1(const st_plan_s* p, int tb, Geo1& g) {
     return true;
 }
 
+struct GeoB {
+    int32_t tiles_x, tiles_y, chunk_z, chunks_z;
+};
+
+// 3D boxes: tiles of 64*VX x NW*K cells (one step, no halo), z chunks sized
+// to fill the device; 32-bit plane offsets.
+bool geob(const st_plan_s* p, const Candidate& c, GeoB& g) {
+    const int64_t* n = p->n;
+    if (n[1] * n[2] * elem_bytes(p->dtype) >= (int64_t(1) << 31)) return false;
+    if (n[0] >= (int64_t(1) << 30) || n[1] >= (int64_t(1) << 30) || n[2] >= (int64_t(1) << 30)) return false;
+    g.tiles_x = static_cast<int32_t>(ceil_div(n[2], 64 * box3d_vx(p->dtype)));
+    g.tiles_y = static_cast<int32_t>(ceil_div(n[1], kBox3DK * kBox3DNW));
+    const int64_t per_plane = static_cast<int64_t>(g.tiles_x) * g.tiles_y;
+    int64_t chunk = c.chunk;
+    if (chunk <= 0) chunk = pick_chunk(n[0], per_plane, static_cast<int64_t>(device_cus()) * 4, 2, 8);
+    chunk = std::min<int64_t>(chunk, n[0]);
+    g.chunk_z = static_cast<int32_t>(chunk);
+    g.chunks_z = static_cast<int32_t>(ceil_div(n[0], chunk));
+    return per_plane * g.chunks_z < (int64_t(1) << 31);
+}
+
 struct Geo3 {
     int32_t hxa, hya, out_w, out_h, tiles_x, tiles_y, chunk_z, chunks_z;
 };
@@ -410,6 +431,16 @@ void build_candidates(st_plan_s* p) {
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
             return (a.tb == want && a.chunk == 0) > (b.tb == want && b.chunk == 0);
         });
+    }
+    if (!force_naive && p->ndim == 3 && p->cls == kBox && p->radius == 1) {
+        for (int ch : {0, 16, 32, 64}) {
+            Candidate c;
+            c.kernel = ST_KERNEL_BOX3D;
+            c.tb = 1;
+            c.chunk = ch;
+            GeoB g;
+            if ((ch == 0 || ch < p->n[0]) && geob(p, c, g)) fast.push_back(c);
+        }
     }
     if (!force_naive && p->ndim == 1 && p->cls == kStar && stream1d_has(p->dtype, p->radius)) {
         // the whole space-time tile in registers: any depth; deeper passes
@@ -561,6 +592,28 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
             e = launch_naive(p->dtype, a, s);
         }
         if (e != hipSuccess) return hip_fail(e, "naive launch");
+        return ST_OK;
+    }
+    if (c.kernel == ST_KERNEL_BOX3D) {
+        GeoB g;
+        if (!geob(p, c, g)) return fail(ST_ERR_UNSUPPORTED, "3D box tiling infeasible");
+        Box3DArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.src = src;
+        a.dst = dst;
+        a.nz = p->n[0];
+        a.ny = p->n[1];
+        a.nx = p->n[2];
+        a.tiles_x = g.tiles_x;
+        a.tiles_y = g.tiles_y;
+        a.chunks_z = g.chunks_z;
+        a.chunk_z = g.chunk_z;
+        for (int i = 0; i < p->npoints; ++i) a.w[i] = wcan[i];
+        for (int t = 0; t < tb && e == hipSuccess; ++t) {
+            // one step per launch (tb > 1 never reaches here: the family's depth is 1)
+            e = launch_box3d(p->dtype, p->bc == kPeriodic, vec_ok, a, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "box3d launch");
         return ST_OK;
     }
     if (c.kernel == ST_KERNEL_STREAM1D) {
@@ -718,6 +771,7 @@ st_status run_steps(st_plan_s* p, const Candidate& c_in, void* grid, void* work,
     const int vx = c.kernel == ST_KERNEL_STREAM2D   ? c.k2.vx
                    : c.kernel == ST_KERNEL_STREAM3D ? c.k3.vx
                    : c.kernel == ST_KERNEL_STREAM1D ? kStream1DVX
+                   : c.kernel == ST_KERNEL_BOX3D    ? box3d_vx(p->dtype)
                                                     : 1;
     const bool vec_ok = (p->n[2] % vx == 0) && aligned16(grid) && aligned16(work);
     void* src = grid;
@@ -780,6 +834,14 @@ void describe(const st_plan_s* p, const Candidate& c, int index, st_plan_info* i
         info->tile_z = 1;
         info->block = 256;
         info->workgroups = ceil_div(g.items, 4);
+    } else if (c.kernel == ST_KERNEL_BOX3D) {
+        GeoB g;
+        geob(p, c, g);
+        info->tile_x = 64 * box3d_vx(p->dtype);
+        info->tile_y = kBox3DK * kBox3DNW;
+        info->tile_z = g.chunk_z;
+        info->block = 64 * kBox3DNW;
+        info->workgroups = static_cast<int64_t>(g.tiles_x) * g.tiles_y * g.chunks_z;
     } else if (c.kernel == ST_KERNEL_STREAM1D) {
         Geo1 g;
         geo1(p, c.tb, g);

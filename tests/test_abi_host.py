@@ -44,10 +44,12 @@ def test_star_and_box_classification_and_families():
     assert p.info()["shape_class"] == 2 and p.info()["kernel"] == st.KERNEL_STREAM2D
     p = st.Plan(synth.star_offsets(2, 1), (100, 300), "bf16")
     assert p.info()["kernel"] == st.KERNEL_STREAM2D
-    # general point sets and 3D boxes run on the one-step kernel
+    # general point sets and radius-2 3D boxes run on the one-step kernel
     p = st.Plan([(0, 0), (0, 1), (-2, 0)], (50, 50), "f64")
     assert p.info()["shape_class"] == 0 and p.info()["kernel"] == st.KERNEL_NAIVE
     p = st.Plan(synth.box_offsets(3, 1), (20, 20, 20), "f64")
+    assert p.info()["shape_class"] == 2 and p.info()["kernel"] == st.KERNEL_BOX3D
+    p = st.Plan(synth.box_offsets(3, 2), (20, 20, 20), "f64")
     assert p.info()["shape_class"] == 2 and p.info()["kernel"] == st.KERNEL_NAIVE
     # 1D stars of radius 1 and 2 run on the strip kernel; other 1D sets one step at a time
     p = st.Plan(synth.star_offsets(1, 2), (1000,), "f64")

@@ -233,3 +233,29 @@ def test_1d_star_all_candidates_match_oracle(dtype, bc, radius, n):
     assert plan.candidates()[0]["kernel"] == 4 or n < 64 * 16
     for k, r in enumerate(results[1:], 1):
         assert np.array_equal(r, results[0]), f"candidate {k} differs bitwise"
+
+
+# ---------------------------------------------------------------------------
+# 3D boxes (Tab. 1 Box-3D27P): the streaming kernel against the oracle and,
+# bit for bit, against the one-step kernel
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+@pytest.mark.parametrize("shape", [(9, 13, 21), (20, 37, 300), (35, 40, 129), (6, 16, 256)])
+def test_3d_box27_all_candidates_match_oracle(dtype, bc, shape):
+    import paper_2303_08365_amd as st
+    offs = synth.box_offsets(3, 1)
+    w = _weights(offs, 7, dtype)
+    steps = 3 if dtype == "bf16" else 5
+    u0 = synth.uniform_field(shape, seed=8)
+    ref = oracle_ref(u0, offs, w, steps, bc, dtype)
+    plan = st.Plan(offs, shape, dtype, bc)
+    assert plan.info()["kernel"] == st.KERNEL_BOX3D
+    results = []
+    for k, c in enumerate(plan.candidates()):
+        print(f"box27 {dtype} {bc} {shape} cand {k} kernel {c['kernel']} chunk {c['tile_z']}", flush=True)
+        got, _ = gpu_sweep(u0, offs, w, steps, bc, dtype, select={"variant": k}, plan=plan)
+        check(got, ref, dtype, steps, f"cand {k}")
+        results.append(got)
+    for k, r in enumerate(results[1:], 1):
+        assert np.array_equal(r, results[0]), f"candidate {k} differs bitwise"
