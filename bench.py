@@ -232,6 +232,24 @@ def heat1d(torch, st, synth, dtype, select=None, n=10_000_000, steps=1000, alpha
     return w
 
 
+def box27(torch, st, synth, dtype, select=None, n=512, steps=20):
+    """Tab. 1's Box-3D27P shape class on the 512^3 grid: 27 weights of 1/27
+    (centre-adjusted), zero rule, U[0,1) seed 0."""
+    w = Workload()
+    shape = (n, n, n)
+    w.coeffs = list(synth.box_mean_weights(3, 1, "f64" if dtype == "f64" else "f32"))
+    w.u = torch.from_numpy(synth.uniform_field(shape, seed=0)).to("cuda", _tdt(torch, dtype))
+    w.work = torch.empty_like(w.u)
+    w.plan = st.Plan(synth.box_offsets(3, 1), shape, dtype, "zero", autotune=select is None)
+    if select:
+        w.plan.select(**select)
+    w.steps, w.cells, w.dtype = steps, n ** 3, dtype
+    w.name = f"3D 27-point box stencil, {n}^3, {steps} steps, zero boundary"
+    w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
+    w.kernel_tb = w.plan.info()["tb"]
+    return w
+
+
 def box2d(torch, st, synth, dtype, select=None, n=8192, steps=1000):
     w = Workload()
     shape = (n, n)
@@ -383,11 +401,11 @@ def case_study(torch, st, synth, steps, n=9600, mu=0.23, amplitude=100.0, sigma=
 
 
 WORKLOADS = {"varcoef": varcoef, "heat3d": heat3d, "heat2d": heat2d, "box2d": box2d, "star25": star25, "batch": batch,
-             "heat1d": heat1d, "star1d5": lambda *a, **k: heat1d(*a, radius=2, **k)}
+             "heat1d": heat1d, "star1d5": lambda *a, **k: heat1d(*a, radius=2, **k), "box27": box27}
 DEFAULT_DTYPE = {"varcoef": "f32", "heat3d": "f64", "heat2d": "f64", "box2d": "f32", "star25": "f32", "batch": "f32",
-                 "heat1d": "f64", "star1d5": "f64"}
+                 "heat1d": "f64", "star1d5": "f64", "box27": "f64"}
 KERNEL_NAMES = {0: "naive_kernel", 1: "stream2d_kernel", 2: "stream3d_kernel", 3: "varcoef3d_kernel",
-                4: "stream1d_kernel"}
+                4: "stream1d_kernel", 5: "box3d_kernel"}
 
 
 def measure(torch, w, steps, warmup):
