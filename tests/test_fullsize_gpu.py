@@ -197,3 +197,45 @@ def test_varcoef_256_gradients_match_directional_fd_and_fp64():
     print(f"FD u {fd_u:.10e} vs {an_u:.10e}; FD k {fd_k:.10e} vs {an_k:.10e}", flush=True)
     assert abs(fd_u - an_u) <= 1e-6 * abs(an_u)
     assert abs(fd_k - an_k) <= 1e-6 * abs(an_k)
+
+
+@pytest.mark.parametrize("radius,weights", [(1, (0.5, 0.25, 0.25)), (2, (0.75, 0.0625, 0.0625, 0.0625, 0.0625))])
+def test_tab1_1d_1e7_cells_1000_steps_sampled_cells(radius, weights):
+    # Heat-1D / Star-1D5P at 10^7 cells, the autotuned plan bench.py times
+    import paper_2303_08365_amd as st
+    import torch
+    n, T = 10_000_000, 1000
+    offs = synth.star_offsets(1, radius)
+    w = synth.adjust_centre(list(weights), "f64")
+    u0 = synth.uniform_field((n,), seed=0)
+    plan = st.Plan(offs, (n,), "f64", "zero", autotune=True)
+    print("plan", plan.info(), flush=True)
+    assert plan.info()["kernel"] == st.KERNEL_STREAM1D
+    g = to_device(u0, "f64")
+    plan.run(g, list(w), T, work=torch.empty_like(g))
+    got = to_host(g)
+    for p in [0, 1, 1023, 1024, 4_999_999, 9_999_999, 9_999_000, 7_654_321]:
+        ref = oracle.sweep_point(u0, offs, w, T, (p,), bc="zero")
+        assert abs(got[p] - ref) <= 1e-12 * max(1.0, abs(ref)), p
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_box27_512_sampled_cells(dtype):
+    # Box-3D27P shape class at 512^3, 20 steps, the plan bench.py times
+    import paper_2303_08365_amd as st
+    import torch
+    n, T = 512, 20
+    offs = synth.box_offsets(3, 1)
+    w = synth.box_mean_weights(3, 1, "f64" if dtype == "f64" else "f32")
+    u0 = synth.round_to(synth.uniform_field((n, n, n), seed=0), dtype)
+    plan = st.Plan(offs, (n, n, n), dtype, "zero", autotune=True)
+    print("plan", plan.info(), flush=True)
+    assert plan.info()["kernel"] == st.KERNEL_BOX3D
+    g = to_device(u0, dtype)
+    plan.run(g, list(w), T, work=torch.empty_like(g))
+    got = to_host(g)
+    del g
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    for p in [(0, 0, 0), (511, 511, 511), (0, 255, 511), (256, 0, 300), (137, 402, 3), (300, 127, 128)]:
+        ref = oracle.sweep_point(u0, offs, w, T, p, bc="zero")
+        assert abs(got[p] - ref) <= tol * max(1.0, abs(ref)), p
