@@ -37,19 +37,23 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 
 
+# Device sources of the kernels whose counters profiles/traffic.json holds:
+# the 3D streaming family (the headline) and the copy kernel that scales the
+# counters.  Host planning code is left out: the launch configuration is part
+# of the lookup key instead.
+TRAFFIC_SOURCES = ("dev_common.h", "internal.h", "registry.h", "stream3d_impl.h", "s3d_r1_f64.hip",
+                   "s3d_r1_f32.hip", "s3d_r1_bf16.hip", "copy.hip")
+
+
 def source_hash() -> str:
-    """SHA-256 over the device-code sources of the library (the .hip files and
-    the headers they include; names and bytes).  Host planning code is left
-    out: the launch configuration is part of the lookup key instead."""
-    import glob
+    """SHA-256 over TRAFFIC_SOURCES (names and bytes)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2303_08365_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*"))):
-        if f.endswith((".h", ".hip")):
-            h.update(os.path.basename(f).encode())
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+    for name in TRAFFIC_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
