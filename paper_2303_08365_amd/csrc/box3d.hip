@@ -1,35 +1,41 @@
-// box3d.hip -- 3D radius-1 boxes (27 points), one step per pass, planes
-// streamed along z.
+// box3d.hip -- 3D radius-1 boxes (27 points), T_b = 1 or 2 steps per pass,
+// planes streamed along z.
 //
 // 2.5-D blocking (paper Sec. 4.1 builds space-time tiles, Sec. 4.2 stages
 // them on chip): a work-group holds an xy tile of 64*VX columns by NW*K rows
-// and streams the planes of a z chunk.  Lane L of wave w holds columns
-// X0 + L*VX .. + VX - 1 of rows Y0 + w*K - 1 .. Y0 + w*K + K: its K rows plus
-// the row above and below (other waves' rows, loaded again from L2), for the
-// last three planes (the z queue) and one plane being prefetched.  The
-// columns just outside the tile come from one load per plane (lanes 0..K+1
-// fetch the left column of the K+2 rows, lanes 32..32+K+1 the right one) and
-// enter lane 0 / lane 63 as the DPP "old" operand through readlane.  Every
-// load is a buffer load through a descriptor whose range is the row (the
-// plane for the outer columns), empty outside the grid, so the zero rule's
-// ghost cells load as 0.
+// and streams the planes of a z chunk; every wave works on its own.  Lane L
+// of wave w holds columns X0 + L*VX .. + VX - 1 of its K rows plus T_b rows
+// above and below (other waves' rows, loaded again from L2): step l (0-based)
+// is computed on K + 2(T_b - 1 - l) rows, so the last step yields exactly the
+// wave's K rows without any exchange between waves.  Each step keeps the last
+// three planes of its input (its z queue).  x neighbours come from the
+// neighbouring lanes by DPP; at step 0 the columns just outside the tile come
+// from one load per plane (lanes 0.. fetch the left column of the rows,
+// lanes 32.. the right one) and enter lane 0 / lane 63 as the DPP "old"
+// operand through readlane; deeper steps lose one column per side, so tiles
+// overlap by whole lanes (zero rule: the edge tiles move inward and the zero
+// entering through DPP is the ghost cell).  Every load is a buffer load
+// through a descriptor whose range is the row (the plane for the outer
+// columns), empty outside the grid, so the zero rule's ghost cells load as 0;
+// intermediate steps zero their ghost planes and rows explicitly.
 //
 // Canonical point order: centre, then (dz, dy, dx) lexicographic -- the
-// one-step kernel's order, one multiply then an FMA chain, so both give the
-// same bits.  At 27 FMAs per cell one step per pass stays bound by HBM.
+// one-step kernel's order, one multiply then an FMA chain, so all depths give
+// the same bits.
 #include "dev_common.h"
 
 namespace st {
 namespace b3d {
 
-template <typename TS, int VX, int K, int NW, bool PER, bool FAST>
+template <typename TS, int VX, int K, int NW, int TB, bool PER, bool FAST>
 struct Kern {
     using S = Storage<TS>;
     using TC = typename S::TC;
     static constexpr int W = 64 * VX;
     static constexpr int H = NW * K;
-    static constexpr int ROWS = K + 2;
-    static_assert(ROWS <= 32, "the outer columns of a wave's rows fit in half a wave");
+    static constexpr int RIN = K + 2 * TB;                  // rows of the input planes
+    static constexpr int HX = ((TB - 1) + VX - 1) / VX * VX;  // stale columns per tile side
+    static_assert(RIN <= 32, "the outer columns of a wave's rows fit in half a wave");
     static constexpr int32_t kRsrcWord3 = 0x00020000;
     static constexpr int32_t kNT = 2;
 
@@ -39,8 +45,9 @@ struct Kern {
         int32_t nz, ny, nx;
         int64_t plane_elems;
         uint32_t row_bytes, plane_bytes;
-        int32_t yr[ROWS];       // grid rows of the wave's rows (wrapped when periodic)
+        int32_t yr[RIN];        // grid rows loaded (wrapped when periodic)
         int32_t yw;             // first owned row of the wave
+        int32_t xl;             // first column of this lane
         int32_t zs, ze;
         uint32_t lo;            // byte offset of the lane's first column
         uint32_t eo[VX];        // element offsets (element-wise access)
@@ -52,9 +59,12 @@ struct Kern {
         TC w[27];
     };
 
-    struct Plane {
-        TC v[ROWS][VX];
-        TC xr;  // outer-column value fetched by this lane
+    template <int TB_>
+    struct State {
+        TC q[TB_][3][RIN][VX];  // step l's z queue (rows used: K + 2(TB - l))
+        TC xr[3];               // outer-column values of step 0's queued planes
+        TC pf[RIN][VX];         // the prefetched input plane
+        TC pfx;
     };
 
     static __device__ __forceinline__ bool ghost(int32_t i, int32_t n) {
@@ -117,26 +127,26 @@ struct Kern {
         }
     }
 
-    // Plane zz (already wrapped when periodic; any value under the zero rule).
-    static __device__ __forceinline__ void load_plane(const Ctx& c, int32_t zz, Plane& p) {
+    // Input plane zz (already wrapped when periodic; any value under the zero rule).
+    static __device__ __forceinline__ void load_plane(const Ctx& c, int32_t zz, TC (&v)[RIN][VX], TC& xr) {
         const bool zout = ghost(zz, c.nz);
         const TS* pbase = zout ? c.src : c.src + static_cast<int64_t>(zz) * c.plane_elems;
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
+        for (int r = 0; r < RIN; ++r) {
             const bool out = zout || ghost(c.yr[r], c.ny);
             const TS* base = out ? c.src : pbase + c.yr[r] * c.nx;
             const __amdgpu_buffer_rsrc_t rs =
                 __builtin_amdgcn_make_buffer_rsrc(const_cast<TS*>(base), 0, out ? 0 : c.row_bytes, kRsrcWord3);
             if constexpr (FAST) {
-                bloadv(rs, c.lo, p.v[r]);
+                bloadv(rs, c.lo, v[r]);
             } else {
 #pragma unroll
-                for (int e = 0; e < VX; ++e) p.v[r][e] = bload1(rs, c.eo[e]);
+                for (int e = 0; e < VX; ++e) v[r][e] = bload1(rs, c.eo[e]);
             }
         }
         const __amdgpu_buffer_rsrc_t rp =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<TS*>(pbase), 0, zout ? 0 : c.plane_bytes, kRsrcWord3);
-        p.xr = bload1(rp, c.xr_off);
+        xr = bload1(rp, c.xr_off);
     }
 
     static __device__ __forceinline__ TC lane_value(TC v, int src_lane) {
@@ -150,24 +160,38 @@ struct Kern {
         }
     }
 
-    // Output plane from the queue (planes z-1, z, z+1 in slots a, b, cc).
-    static __device__ __forceinline__ void compute(const Ctx& c, const Plane* const (&pl)[3], TC (&out)[K][VX]) {
-        // x neighbours of every queued row: lane 0 / 63 take the outer column
-        TC lft[3][ROWS], rgt[3][ROWS];
+    // Step L on its queue (slot (J+1+s) % 3 holds plane zc - 1 + s): the
+    // RO = K + 2(TB-1-L) output rows of plane zc; output row o reads queue
+    // rows o .. o+2.
+    template <int L, int J>
+    static __device__ __forceinline__ void compute(const Ctx& c, const State<TB>& st,
+                                                   TC (&out)[K + 2 * (TB - 1 - L)][VX]) {
+        constexpr int RL = K + 2 * (TB - L);  // rows of this step's queue
+        constexpr int RO = RL - 2;
+        TC lft[3][RL], rgt[3][RL];
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const TC xg = c.xr_zero ? TC(0) : pl[s]->xr;
+            const int sl = (J + 1 + s) % 3;
+            if constexpr (L == 0) {
+                const TC xg = c.xr_zero ? TC(0) : st.xr[sl];
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) {
-                lft[s][r] = from_lower(pl[s]->v[r][VX - 1], lane_value(xg, r));
-                rgt[s][r] = from_upper(pl[s]->v[r][0], lane_value(xg, 32 + r));
+                for (int r = 0; r < RL; ++r) {
+                    lft[s][r] = from_lower(st.q[0][sl][r][VX - 1], lane_value(xg, r));
+                    rgt[s][r] = from_upper(st.q[0][sl][r][0], lane_value(xg, 32 + r));
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < RL; ++r) {
+                    lft[s][r] = from_lower_z(st.q[L][sl][r][VX - 1]);
+                    rgt[s][r] = from_upper_z(st.q[L][sl][r][0]);
+                }
             }
         }
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int o = 0; o < RO; ++o) {
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                TC acc = c.w[0] * pl[1]->v[k + 1][e];
+                TC acc = c.w[0] * st.q[L][(J + 2) % 3][o + 1][e];
                 int p = 1;
 #pragma unroll
                 for (int dz = -1; dz <= 1; ++dz)
@@ -176,12 +200,31 @@ struct Kern {
 #pragma unroll
                         for (int dx = -1; dx <= 1; ++dx) {
                             if (dz == 0 && dy == 0 && dx == 0) continue;
-                            const int s = dz + 1, r = k + 1 + dy, x = e + dx;
-                            const TC v = x < 0 ? lft[s][r] : (x >= VX ? rgt[s][r] : pl[s]->v[r][x < 0 ? 0 : (x >= VX ? 0 : x)]);
+                            const int s = dz + 1, r = o + 1 + dy, x = e + dx;
+                            const int sl = (J + 1 + s) % 3;
+                            const TC v = x < 0 ? lft[s][r]
+                                               : (x >= VX ? rgt[s][r] : st.q[L][sl][r][x < 0 ? 0 : (x >= VX ? 0 : x)]);
                             acc = fma_c(c.w[p], v, acc);
                             ++p;
                         }
-                out[k][e] = acc;
+                out[o][e] = acc;
+            }
+        }
+    }
+
+    // Zero rule: the ghost cells of an intermediate step stay 0 (plane, rows,
+    // and columns when the tile is not moved inward); bfloat16 rounds.
+    template <int L>
+    static __device__ __forceinline__ void finish(const Ctx& c, int32_t zc, TC (&out)[K + 2 * (TB - 1 - L)][VX]) {
+        constexpr int RO = K + 2 * (TB - 1 - L);
+        const bool zg = ghost(zc, c.nz);
+#pragma unroll
+        for (int o = 0; o < RO; ++o) {
+            const bool rg = zg || ghost(c.yw - (TB - 1 - L) + o, c.ny);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const bool g = rg || (!FAST && ghost(c.xl + e, c.nx));
+                out[o][e] = g ? TC(0) : S::round(out[o][e]);
             }
         }
     }
@@ -205,16 +248,35 @@ struct Kern {
 
     static __device__ __forceinline__ int32_t wz(const Ctx& c, int32_t z) { return PER ? wrap_idx(z, c.nz) : z; }
 
-    // Slot J of a group of three: the queue is planes (J+1)%3, (J+2)%3, J
-    // (oldest first) after loading plane zin into slot J.
+    // Step L of the iteration that took input plane zin into slot J: plane
+    // zin - (L+1); its output enters step L+1's queue at slot J.
+    template <int L, int J>
+    static __device__ __forceinline__ void level(const Ctx& c, int32_t zin, State<TB>& st) {
+        constexpr int RO = K + 2 * (TB - 1 - L);
+        TC out[RO][VX];
+        compute<L, J>(c, st, out);
+        const int32_t zc = zin - (L + 1);
+        if constexpr (L + 1 == TB) {
+            store_plane(c, zc, out);
+        } else {
+            finish<L>(c, zc, out);
+#pragma unroll
+            for (int o = 0; o < RO; ++o)
+#pragma unroll
+                for (int e = 0; e < VX; ++e) st.q[L + 1][J][o][e] = out[o][e];
+            level<L + 1, J>(c, zin, st);
+        }
+    }
+
     template <int J>
-    static __device__ __forceinline__ void step(const Ctx& c, int32_t zin, int32_t zlast, Plane (&q)[3], Plane& pf) {
-        q[J] = pf;
-        load_plane(c, wz(c, zin + 1 <= zlast ? zin + 1 : zlast), pf);
-        const Plane* const pl[3] = {&q[(J + 1) % 3], &q[(J + 2) % 3], &q[J]};
-        TC out[K][VX];
-        compute(c, pl, out);
-        store_plane(c, zin - 1, out);
+    static __device__ __forceinline__ void step(const Ctx& c, int32_t zin, int32_t zlast, State<TB>& st) {
+#pragma unroll
+        for (int r = 0; r < RIN; ++r)
+#pragma unroll
+            for (int e = 0; e < VX; ++e) st.q[0][J][r][e] = st.pf[r][e];
+        st.xr[J] = st.pfx;
+        load_plane(c, wz(c, zin + 1 <= zlast ? zin + 1 : zlast), st.pf, st.pfx);
+        level<0, J>(c, zin, st);
     }
 
     static __device__ __forceinline__ void run(const Box3DArgs& a) {
@@ -236,24 +298,25 @@ struct Kern {
         c.plane_elems = a.ny * a.nx;
         c.row_bytes = static_cast<uint32_t>(c.nx) * sizeof(TS);
         c.plane_bytes = static_cast<uint32_t>(c.plane_elems) * sizeof(TS);
-        const int32_t X0 = tx * W;
-        const int32_t Y0 = ty * H;
-        c.ox0 = X0;
-        c.ox1 = X0 + W < c.nx ? X0 + W : c.nx;
-        const int32_t xl = X0 + c.lane * VX;
-        c.yw = Y0 + wave * K;
+        constexpr int32_t OUTW = W - 2 * HX;
+        c.ox0 = tx * OUTW;
+        c.ox1 = c.ox0 + OUTW < c.nx ? c.ox0 + OUTW : c.nx;
+        int32_t X0 = c.ox0 - HX;
+        if (!PER && FAST) X0 = X0 < 0 ? 0 : (X0 + W > c.nx ? c.nx - W : X0);
+        c.xl = X0 + c.lane * VX;
+        c.yw = ty * H + wave * K;
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) c.yr[r] = PER ? wrap_idx(c.yw - 1 + r, c.ny) : c.yw - 1 + r;
-        c.lo = static_cast<uint32_t>(PER ? wrap_idx(xl, c.nx) : xl) * sizeof(TS);
+        for (int r = 0; r < RIN; ++r) c.yr[r] = PER ? wrap_idx(c.yw - TB + r, c.ny) : c.yw - TB + r;
+        c.lo = static_cast<uint32_t>(PER ? wrap_idx(c.xl, c.nx) : c.xl) * sizeof(TS);
 #pragma unroll
         for (int e = 0; e < VX; ++e)
-            c.eo[e] = static_cast<uint32_t>(PER ? wrap_idx(xl + e, c.nx) : xl + e) * sizeof(TS);
+            c.eo[e] = static_cast<uint32_t>(PER ? wrap_idx(c.xl + e, c.nx) : c.xl + e) * sizeof(TS);
         {
             const bool right = c.lane >= 32;
             const int r = right ? c.lane - 32 : c.lane;
-            const int32_t rr = r < ROWS ? r : 0;
+            const int32_t rr = r < RIN ? r : 0;
             const int32_t xx = right ? X0 + W : X0 - 1;
-            const int32_t y = c.yw - 1 + rr;
+            const int32_t y = c.yw - TB + rr;
             const int32_t ry = PER ? wrap_idx(y, c.ny) : y;
             const int32_t rx = PER ? wrap_idx(xx, c.nx) : xx;
             // a ghost row gives an offset outside the plane (loads 0); a ghost
@@ -261,63 +324,85 @@ struct Kern {
             c.xr_off = static_cast<uint32_t>(ry * c.nx + rx) * sizeof(TS);
             c.xr_zero = ghost(xx, c.nx);
         }
-        c.so = static_cast<uint32_t>(xl - c.ox0) * sizeof(TS);
+        c.so = static_cast<uint32_t>(c.xl - c.ox0) * sizeof(TS);
         c.out_bytes = static_cast<uint32_t>(c.ox1 - c.ox0) * sizeof(TS);
         c.zs = cz * a.chunk_z;
         c.ze = c.zs + a.chunk_z < c.nz ? c.zs + a.chunk_z : c.nz;
 #pragma unroll
         for (int p = 0; p < 27; ++p) c.w[p] = static_cast<TC>(a.w[p]);
 
-        // stream planes zs-1 .. ze: output plane zin-1 once zin-1 >= zs
-        const int32_t zfirst = c.zs - 1, zlast = c.ze;
-        Plane q[3], pf;
-        load_plane(c, wz(c, zfirst), q[1]);
-        load_plane(c, wz(c, zfirst + 1), q[2]);
-        load_plane(c, wz(c, zfirst + 2 <= zlast ? zfirst + 2 : zlast), pf);
-        // the queue before the first step is (q[1], q[2]); step J = 0 loads slot 0
-        int32_t zin = zfirst + 2;
+        // stream planes zs-TB .. ze-1+TB; the last step outputs plane zin-TB
+        const int32_t zfirst = c.zs - TB, zlast = c.ze - 1 + TB;
+        State<TB> st;
+#pragma unroll
+        for (int l = 0; l < TB; ++l)
+#pragma unroll
+            for (int s = 0; s < 3; ++s)
+#pragma unroll
+                for (int r = 0; r < RIN; ++r)
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) st.q[l][s][r][e] = TC(0);
+#pragma unroll
+        for (int s = 0; s < 3; ++s) st.xr[s] = TC(0);
+        load_plane(c, wz(c, zfirst), st.pf, st.pfx);
+        int32_t zin = zfirst;
         for (; zin + 2 <= zlast; zin += 3) {
-            step<0>(c, zin, zlast, q, pf);
-            step<1>(c, zin + 1, zlast, q, pf);
-            step<2>(c, zin + 2, zlast, q, pf);
+            step<0>(c, zin, zlast, st);
+            step<1>(c, zin + 1, zlast, st);
+            step<2>(c, zin + 2, zlast, st);
         }
-        if (zin <= zlast) step<0>(c, zin, zlast, q, pf);
-        if (zin + 1 <= zlast) step<1>(c, zin + 1, zlast, q, pf);
+        if (zin <= zlast) step<0>(c, zin, zlast, st);
+        if (zin + 1 <= zlast) step<1>(c, zin + 1, zlast, st);
     }
 };
 
-template <typename TS, int VX, int K, int NW, bool PER, bool FAST>
+template <typename TS, int VX, int K, int NW, int TB, bool PER, bool FAST>
 __global__ __launch_bounds__(64 * NW) void box3d_kernel(const Box3DArgs a) {
-    Kern<TS, VX, K, NW, PER, FAST>::run(a);
+    Kern<TS, VX, K, NW, TB, PER, FAST>::run(a);
 }
 
-template <typename TS, int VX>
+template <typename TS, int VX, int K, int NW, int TB>
 hipError_t launch_t(bool per, bool fast, const Box3DArgs& a, hipStream_t s) {
-    constexpr int K = kBox3DK, NW = kBox3DNW;
     const int64_t tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
     const dim3 grid(static_cast<unsigned>(tiles)), block(64 * NW);
     if (per) {
-        if (fast) hipLaunchKernelGGL((box3d_kernel<TS, VX, K, NW, true, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((box3d_kernel<TS, VX, K, NW, true, false>), grid, block, 0, s, a);
+        if (fast) hipLaunchKernelGGL((box3d_kernel<TS, VX, K, NW, TB, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((box3d_kernel<TS, VX, K, NW, TB, true, false>), grid, block, 0, s, a);
     } else {
-        if (fast) hipLaunchKernelGGL((box3d_kernel<TS, VX, K, NW, false, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((box3d_kernel<TS, VX, K, NW, false, false>), grid, block, 0, s, a);
+        if (fast) hipLaunchKernelGGL((box3d_kernel<TS, VX, K, NW, TB, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((box3d_kernel<TS, VX, K, NW, TB, false, false>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }
 
 }  // namespace b3d
 
-int box3d_vx(int dtype) { return dtype == kF64 ? 2 : 4; }
+Box3DShape box3d_shape(int dtype, int tb) {
+    const int vx = dtype == kF64 ? 2 : 4;
+    const int k = tb == 1 ? 4 : 2, nw = tb == 1 ? 4 : 8;
+    const int hx = ((tb - 1) + vx - 1) / vx * vx;
+    return Box3DShape{vx, 64 * vx, k * nw, 64 * vx - 2 * hx, 64 * nw};
+}
 
 hipError_t launch_box3d(int dtype, bool periodic, bool fast, const Box3DArgs& a, hipStream_t s) {
     if (static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z <= 0) return hipSuccess;
-    switch (dtype) {
-        case kF64: return b3d::launch_t<double, 2>(periodic, fast, a, s);
-        case kF32: return b3d::launch_t<float, 4>(periodic, fast, a, s);
-        case kBF16: return b3d::launch_t<bf16s, 4>(periodic, fast, a, s);
-        default: return hipErrorInvalidValue;
+    if (a.tb == 1) {
+        switch (dtype) {
+            case kF64: return b3d::launch_t<double, 2, 4, 4, 1>(periodic, fast, a, s);
+            case kF32: return b3d::launch_t<float, 4, 4, 4, 1>(periodic, fast, a, s);
+            case kBF16: return b3d::launch_t<bf16s, 4, 4, 4, 1>(periodic, fast, a, s);
+            default: return hipErrorInvalidValue;
+        }
     }
+    if (a.tb == 2) {
+        switch (dtype) {
+            case kF64: return b3d::launch_t<double, 2, 2, 8, 2>(periodic, fast, a, s);
+            case kF32: return b3d::launch_t<float, 4, 2, 8, 2>(periodic, fast, a, s);
+            case kBF16: return b3d::launch_t<bf16s, 4, 2, 8, 2>(periodic, fast, a, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace st

@@ -111,16 +111,22 @@ hipError_t launch_stream1d(int dtype, int radius, bool periodic, const Stream1DA
 // ----------------------------------------------------------------------------
 // 3D radius-1 boxes (27 points): one step per pass, planes streamed along z
 // ----------------------------------------------------------------------------
-constexpr int kBox3DK = 4;   // rows per wave
-constexpr int kBox3DNW = 4;  // waves per work-group
 struct Box3DArgs {
     const void* src;
     void* dst;
     int64_t nz, ny, nx;
     int32_t tiles_x, tiles_y, chunks_z, chunk_z;
+    int32_t tb;          // steps per pass: 1 or 2
     double w[27];        // canonical-order weights
 };
-int box3d_vx(int dtype);  // columns per lane
+struct Box3DShape {
+    int vx;              // columns per lane
+    int w;               // register tile width 64*vx
+    int h;               // owned rows per tile (rows per wave x waves)
+    int out_w;           // owned columns per tile
+    int block;           // threads per work-group
+};
+Box3DShape box3d_shape(int dtype, int tb);
 hipError_t launch_box3d(int dtype, bool periodic, bool fast, const Box3DArgs& a, hipStream_t s);
 
 // ----------------------------------------------------------------------------

@@ -241,7 +241,7 @@ def test_1d_star_all_candidates_match_oracle(dtype, bc, radius, n):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("bc", ["zero", "periodic"])
-@pytest.mark.parametrize("shape", [(9, 13, 21), (20, 37, 300), (35, 40, 129), (6, 16, 256)])
+@pytest.mark.parametrize("shape", [(9, 13, 21), (20, 37, 300), (35, 40, 129), (6, 16, 256), (10, 20, 64)])
 def test_3d_box27_all_candidates_match_oracle(dtype, bc, shape):
     import paper_2303_08365_amd as st
     offs = synth.box_offsets(3, 1)
@@ -253,7 +253,7 @@ def test_3d_box27_all_candidates_match_oracle(dtype, bc, shape):
     assert plan.info()["kernel"] == st.KERNEL_BOX3D
     results = []
     for k, c in enumerate(plan.candidates()):
-        print(f"box27 {dtype} {bc} {shape} cand {k} kernel {c['kernel']} chunk {c['tile_z']}", flush=True)
+        print(f"box27 {dtype} {bc} {shape} cand {k} kernel {c['kernel']} tb {c['tb']} chunk {c['tile_z']}", flush=True)
         got, _ = gpu_sweep(u0, offs, w, steps, bc, dtype, select={"variant": k}, plan=plan)
         check(got, ref, dtype, steps, f"cand {k}")
         results.append(got)
