@@ -126,6 +126,22 @@ typedef struct {
 st_status stencil_plan(st_plan* out, const st_pattern* pattern, const int64_t* shape,
                        st_dtype storage, st_boundary bc, uint32_t flags);
 
+/*
+ * stencil_autotune_cache -- remember autotuning results (paper Sec. 5.2: the
+ * scheduler's choice comes from a profile of the problem, taken once).  Every
+ * ST_PLAN_AUTOTUNE plan (single or batch) first looks its key up -- device
+ * (architecture and compute-unit count), dimensions, storage type, boundary,
+ * shape or shapes, point offsets -- and takes the stored candidate without
+ * timing anything; otherwise it times the candidates and stores its choice.
+ * The in-memory table lives as long as the library.
+ *   path  text file, one "key<TAB>candidate<TAB>candidates" line per plan:
+ *         read now when it exists (its entries join the table) and rewritten
+ *         after every new tuning (a file that cannot be written is left as
+ *         it is: the cache is advisory).  NULL stops writing a file.
+ * Errors: ST_ERR_ARG for an empty path or a malformed file (nothing loaded).
+ */
+st_status stencil_autotune_cache(const char* path);
+
 /* Release a plan and everything it owns (NULL is accepted). */
 st_status stencil_plan_destroy(st_plan plan);
 

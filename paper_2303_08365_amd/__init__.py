@@ -20,7 +20,7 @@ __all__ = [
     "F64", "F32", "BF16", "BC_ZERO", "BC_PERIODIC", "PLAN_AUTOTUNE", "PLAN_NAIVE",
     "PLAN_VARCOEF", "PLAN_GRAPH", "KERNEL_NAIVE", "KERNEL_STREAM2D", "KERNEL_STREAM3D", "KERNEL_VARCOEF3D",
     "KERNEL_STREAM1D", "KERNEL_BOX3D",
-    "STATUS", "StencilFn", "varcoef_plan", "copy",
+    "STATUS", "StencilFn", "varcoef_plan", "copy", "autotune_cache",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -107,6 +107,7 @@ def library():
             "stencil_adjoint_run": [P, P, ctypes.c_double, p_dbl, ctypes.POINTER(P), i64, i64, P, P, P,
                                     P, P],
             "stencil_copy": [P, P, i64, P],
+            "stencil_autotune_cache": [ctypes.c_char_p],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -342,6 +343,12 @@ class BatchPlan:
         st = (ctypes.c_int64 * n)(*[int(s) for s in steps])
         _check(library().stencil_batch_run(self._h, n, gp, wp, cf, st, _stream_handle(stream)))
         return grids
+
+
+def autotune_cache(path: Optional[str]):
+    """``stencil_autotune_cache``: keep autotuning choices in `path` (a text
+    file read now and rewritten after every new tuning); None stops writing."""
+    _check(library().stencil_autotune_cache(None if path is None else os.fsencode(path)))
 
 
 def copy(dst, src, stream=None):

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -874,9 +875,60 @@ void describe(const st_plan_s* p, const Candidate& c, int index, st_plan_info* i
     }
 }
 
+// ---------------------------------------------------------------------------
+// autotune cache: plan key -> chosen candidate, in memory and optionally in a
+// text file (one "key<TAB>candidate<TAB>candidates" line per plan)
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;
+std::string g_tune_path;
+
+std::string tune_key(const st_plan_s* p) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string devname = "?";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        devname = std::string(prop.gcnArchName) + ":" + std::to_string(prop.multiProcessorCount);
+    std::string k = "v1 " + devname + " nd" + std::to_string(p->ndim) + " t" + std::to_string(p->dtype) + " bc" +
+                    std::to_string(p->bc) + (p->batch ? " batch" : " grid");
+    if (p->batch) {
+        for (const BatchGrid& g : p->grids) k += " " + std::to_string(g.ny) + "x" + std::to_string(g.nx);
+    } else {
+        k += " " + std::to_string(p->n[0]) + "x" + std::to_string(p->n[1]) + "x" + std::to_string(p->n[2]);
+    }
+    k += " p";
+    for (int i = 0; i < p->npoints; ++i)
+        k += " " + std::to_string(p->off[i][0]) + "," + std::to_string(p->off[i][1]) + "," +
+             std::to_string(p->off[i][2]);
+    return k;
+}
+
+bool tune_lookup(st_plan_s* p, const std::string& key) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    const int idx = it->second.first, n = it->second.second;
+    if (n != static_cast<int>(p->cands.size()) || idx < 0 || idx >= n) return false;
+    p->sel = idx;
+    return true;
+}
+
+void tune_store(const std::string& key, int idx, int n) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[key] = {idx, n};
+    if (g_tune_path.empty()) return;
+    // the cache is advisory: a file that cannot be written is left as it is
+    FILE* f = std::fopen(g_tune_path.c_str(), "w");
+    if (!f) return;
+    for (const auto& kv : g_tune) std::fprintf(f, "%s\t%d\t%d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    std::fclose(f);
+}
+
 st_status autotune(st_plan_s* p) {
     if (st_status r = need_device(); r != ST_OK) return r;
     if (p->cands.size() <= 1) return ST_OK;
+    const std::string tkey = tune_key(p);
+    if (tune_lookup(p, tkey)) return ST_OK;
     const size_t bytes = static_cast<size_t>(plan_cells(p)) * elem_bytes(p->dtype);
     void *a = nullptr, *b = nullptr;
     ST_HIP(hipMalloc(&a, bytes), "hipMalloc(autotune)");
@@ -912,6 +964,7 @@ st_status autotune(st_plan_s* p) {
     hipFree(a);
     hipFree(b);
     p->sel = best_i;
+    tune_store(tkey, best_i, static_cast<int>(p->cands.size()));
     g_last_error.clear();
     return ST_OK;
 }
@@ -1417,6 +1470,8 @@ namespace {
 st_status batch_autotune(st_plan_s* p) {
     if (st_status r = need_device(); r != ST_OK) return r;
     if (p->cands.size() <= 1) return ST_OK;
+    const std::string tkey = tune_key(p);
+    if (tune_lookup(p, tkey)) return ST_OK;
     const int n = static_cast<int>(p->grids.size());
     std::vector<void*> g(n, nullptr), w(n, nullptr);
     std::vector<double> coeffs(static_cast<size_t>(n) * p->npoints);
@@ -1463,6 +1518,7 @@ st_status batch_autotune(st_plan_s* p) {
         p->sel = best_i;
         p->table_key.clear();
         p->flags = flags;
+        tune_store(tkey, best_i, static_cast<int>(p->cands.size()));
         g_last_error.clear();
     }
     hipDeviceSynchronize();
@@ -1643,6 +1699,44 @@ extern "C" st_status stencil_adjoint_run(st_plan plan, const void* k, double alp
 // ---------------------------------------------------------------------------
 // bandwidth reference
 // ---------------------------------------------------------------------------
+extern "C" st_status stencil_autotune_cache(const char* path) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (!path) {
+        g_tune_path.clear();
+        return ST_OK;
+    }
+    if (!*path) return fail(ST_ERR_ARG, "empty autotune cache path");
+    std::map<std::string, std::pair<int, int>> loaded;
+    if (FILE* f = std::fopen(path, "r")) {
+        char line[8192];
+        int lineno = 0;
+        while (std::fgets(line, sizeof(line), f)) {
+            ++lineno;
+            std::string l(line);
+            while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+            if (l.empty()) continue;
+            const size_t t2 = l.rfind('\t');
+            const size_t t1 = t2 == std::string::npos || t2 == 0 ? std::string::npos : l.rfind('\t', t2 - 1);
+            char* e1 = nullptr;
+            char* e2 = nullptr;
+            long idx = 0, n = 0;
+            if (t1 != std::string::npos) {
+                idx = std::strtol(l.c_str() + t1 + 1, &e1, 10);
+                n = std::strtol(l.c_str() + t2 + 1, &e2, 10);
+            }
+            if (t1 == std::string::npos || e1 != l.c_str() + t2 || *e2 != '\0' || idx < 0 || n < 1 || idx >= n) {
+                std::fclose(f);
+                return fail(ST_ERR_ARG, "%s:%d: not a 'key<TAB>candidate<TAB>candidates' line", path, lineno);
+            }
+            loaded[l.substr(0, t1)] = {static_cast<int>(idx), static_cast<int>(n)};
+        }
+        std::fclose(f);
+    }
+    for (const auto& kv : loaded) g_tune[kv.first] = kv.second;
+    g_tune_path = path;
+    return ST_OK;
+}
+
 extern "C" st_status stencil_copy(void* dst, const void* src, int64_t bytes, void* stream) {
     if (bytes < 0) return fail(ST_ERR_ARG, "bytes = %lld < 0", static_cast<long long>(bytes));
     if (bytes == 0) return ST_OK;

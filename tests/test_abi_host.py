@@ -258,3 +258,21 @@ def test_3d_streaming_needs_planes_below_2gib():
     big = st.Plan(offs, (2, 16385, 16384), "f64")      # just above 2 GiB
     assert all(c["kernel"] == st.KERNEL_NAIVE for c in big.candidates())
     assert big.info()["kernel"] == st.KERNEL_NAIVE
+
+
+def test_autotune_cache_file_validation(tmp_path):
+    import paper_2303_08365_amd as st
+    bad = tmp_path / "bad.txt"
+    bad.write_text("v1 some key\t3\n")
+    with pytest.raises(st.StencilError):
+        st.autotune_cache(str(bad))
+    bad.write_text("v1 some key\t5\t4\n")  # candidate outside 0..3
+    with pytest.raises(st.StencilError):
+        st.autotune_cache(str(bad))
+    good = tmp_path / "good.txt"
+    good.write_text("v1 dev nd3 t0 bc0 grid 8x8x8 p 0,0,0\t1\t4\n\n")
+    st.autotune_cache(str(good))
+    st.autotune_cache(str(tmp_path / "missing.txt"))  # created on the first tuning
+    st.autotune_cache(None)
+    with pytest.raises(st.StencilError):
+        st.autotune_cache("")

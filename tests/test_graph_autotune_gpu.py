@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import check, oracle_ref, to_device, to_host
+from gpu_helpers import check, gpu_sweep, oracle_ref, to_device, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -82,3 +82,32 @@ def test_autotuned_single_grid_plan_matches_oracle():
     g = to_device(u0, "f64")
     p.run(g, list(w), 10)
     check(to_host(g), oracle_ref(u0, offs, w, 10), "f64", 10, "autotuned")
+
+
+def test_autotune_cache_reuses_and_honours_stored_choice(tmp_path):
+    import paper_2303_08365_amd as st
+    path = tmp_path / "tune.txt"
+    st.autotune_cache(str(path))
+    try:
+        offs = synth.star_offsets(2, 1)
+        shape = (301, 700)
+        p1 = st.Plan(offs, shape, "f32", "zero", autotune=True)
+        # the file holds every choice of this process; ours is the 301 x 700 grid
+        lines = [ln for ln in path.read_text().splitlines() if " grid 1x301x700 " in ln and " t1 " in ln]
+        assert len(lines) == 1
+        key, idx, n = lines[0].split("\t")
+        assert int(idx) == p1.info()["variant"] and int(n) == p1.info()["ncandidates"]
+        p2 = st.Plan(offs, shape, "f32", "zero", autotune=True)
+        assert p2.info()["variant"] == p1.info()["variant"]
+        # a stored choice is taken as it is, without timing
+        other = (int(idx) + 1) % int(n)
+        path.write_text(f"{key}\t{other}\t{n}\n")
+        st.autotune_cache(str(path))
+        p3 = st.Plan(offs, shape, "f32", "zero", autotune=True)
+        assert p3.info()["variant"] == other
+        w = synth.heat_weights(2, 0.2, "f32")
+        u0 = synth.uniform_field(shape, seed=41)
+        got, _ = gpu_sweep(u0, offs, w, 9, "zero", "f32", plan=p3)
+        check(got, oracle_ref(u0, offs, w, 9, "zero", "f32"), "f32", 9, "cached choice")
+    finally:
+        st.autotune_cache(None)
