@@ -20,7 +20,7 @@ __all__ = [
     "F64", "F32", "BF16", "BC_ZERO", "BC_PERIODIC", "PLAN_AUTOTUNE", "PLAN_NAIVE",
     "PLAN_VARCOEF", "PLAN_GRAPH", "KERNEL_NAIVE", "KERNEL_STREAM2D", "KERNEL_STREAM3D", "KERNEL_VARCOEF3D",
     "KERNEL_STREAM1D", "KERNEL_BOX3D",
-    "STATUS", "StencilFn", "varcoef_plan", "copy", "autotune_cache",
+    "STATUS", "StencilFn", "varcoef_plan", "copy", "autotune_cache", "batch_run",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -366,6 +366,24 @@ def run(grid, coeffs, offsets, steps: int, bc="zero", plan: Optional[Plan] = Non
     if plan is None:
         plan = Plan(offsets, tuple(grid.shape), _tensor_dtype(grid), bc)
     return plan.run(grid, coeffs, steps, work=work, stream=stream)
+
+
+def batch_run(grids, coeffs, offsets, steps, bc="zero", plan: Optional[BatchPlan] = None, works=None,
+              stream=None):
+    """One-shot batch: plan (unless given) and run every grid in place.
+    `coeffs` holds one weight row per grid, `steps` one count per grid (or
+    one count for all); `works` defaults to fresh buffers like the grids."""
+    import torch
+    n = len(grids)
+    steps = list(steps) if hasattr(steps, "__len__") else [int(steps)] * n
+    if plan is None:
+        dts = {_tensor_dtype(g) for g in grids}
+        if len(dts) != 1:
+            raise ValueError("all grids of a batch share one dtype")
+        plan = BatchPlan(offsets, [tuple(g.shape) for g in grids], dts.pop(), bc)
+    if works is None:
+        works = [torch.empty_like(g) for g in grids]
+    return plan.run(grids, works, coeffs, steps, stream=stream)
 
 
 _VC_PLANS = {}

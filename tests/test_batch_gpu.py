@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import check, to_device, to_host
+from gpu_helpers import check, oracle_ref, to_device, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -68,3 +68,17 @@ def test_batch_repeated_calls_reuse_the_table():
     for g in range(5):
         ref = oracle.sweep(synth.round_to(u0s[g], "f32"), offs, coeffs[g], 12)
         check(to_host(grids[g]), ref, "f32", 12, f"grid {g}")
+
+
+def test_module_batch_run_matches_oracle():
+    import paper_2303_08365_amd as st
+    offs = synth.star_offsets(2, 1)
+    shapes = [(40, 300), (129, 77), (256, 256)]
+    alphas = [0.1, 0.2, 0.24]
+    steps = [7, 12, 5]
+    u0s = [synth.uniform_field(sh, seed=50 + i) for i, sh in enumerate(shapes)]
+    grids = [to_device(u, "f64") for u in u0s]
+    coeffs = [list(synth.heat_weights(2, a)) for a in alphas]
+    st.batch_run(grids, coeffs, offs, steps)
+    for g, u, w, t in zip(grids, u0s, coeffs, steps):
+        check(to_host(g), oracle_ref(u, offs, w, t, "zero", "f64"), "f64", t, "batch_run")
