@@ -239,3 +239,24 @@ def test_box27_512_sampled_cells(dtype):
     for p in [(0, 0, 0), (511, 511, 511), (0, 255, 511), (256, 0, 300), (137, 402, 3), (300, 127, 128)]:
         ref = oracle.sweep_point(u0, offs, w, T, p, bc="zero")
         assert abs(got[p] - ref) <= tol * max(1.0, abs(ref)), p
+
+
+def test_heat2d_512_fp64_100_steps_as_benched():
+    # the 2D 5-point heat workload (FP64, 512^2, alpha 0.2, 100 steps, zero rule)
+    # with the plan bench.py builds for it (autotuned, graph replay), against the
+    # full oracle sweep, repeated so the replayed graph is checked too
+    import paper_2303_08365_amd as st
+    import torch
+    n, T, alpha = 512, 100, 0.2
+    offs = synth.star_offsets(2, 1)
+    w = synth.heat_weights(2, alpha)
+    u0 = synth.uniform_field((n, n), seed=0)
+    ref = oracle.heat(u0, alpha, T, bc="zero")
+    plan = st.Plan(offs, (n, n), "f64", "zero", graph=True, autotune=True)
+    print("plan", plan.info(), flush=True)
+    work = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        g = to_device(u0, "f64")
+        plan.run(g, list(w), T, work=work)
+        err = oracle.rel_l2(to_host(g), ref)
+        assert err <= 1e-12, (rep, err)
