@@ -39,14 +39,15 @@ TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 
 # Device sources of the kernels whose counters profiles/traffic.json holds:
 # the 3D streaming family (the headline) and the copy kernel that scales the
-# counters.  Host planning code is left out: the launch configuration is part
-# of the lookup key instead.
-TRAFFIC_SOURCES = ("dev_common.h", "internal.h", "registry.h", "stream3d_impl.h", "s3d_r1_f64.hip",
-                   "s3d_r1_f32.hip", "s3d_r1_bf16.hip", "copy.hip")
+# counters; of internal.h only the 3D family's argument block.  Host planning
+# code is left out: the launch configuration is part of the lookup key.
+TRAFFIC_SOURCES = ("dev_common.h", "registry.h", "stream3d_impl.h", "s3d_r1_f64.hip", "s3d_r1_f32.hip",
+                   "s3d_r1_bf16.hip", "copy.hip")
 
 
 def source_hash() -> str:
-    """SHA-256 over TRAFFIC_SOURCES (names and bytes)."""
+    """SHA-256 over TRAFFIC_SOURCES (names and bytes) and the Stream3DArgs /
+    Stream3DKey definitions of internal.h."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2303_08365_amd", "csrc")
@@ -54,6 +55,12 @@ def source_hash() -> str:
         h.update(name.encode())
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "internal.h"), "rb") as fh:
+        text = fh.read()
+    a = text.index(b"struct Stream3DArgs {")
+    b = text.index(b"};", text.index(b"struct Stream3DKey {")) + 2
+    h.update(b"internal.h:3d")
+    h.update(text[a:b])
     return h.hexdigest()
 
 
