@@ -198,7 +198,8 @@ st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs
  *           stencil_run's.
  * The sum is deterministic: partial sums go to a plan-owned device buffer
  * (allocated by the first call that needs it, which is then not capturable)
- * and one work-group adds them in a fixed order.  The fused 3D radius-1
+ * and one work-group adds them in a fixed order.  That buffer belongs to the
+ * plan, so calls on one plan must not overlap on different streams.  The fused 3D radius-1
  * kernels (FP64, FP32, bfloat16 default tilings) sum the outflow inside
  * their passes; every other plan runs one step per pass with a band kernel
  * over the state each step reads.  ST_PLAN_GRAPH is ignored here (the
