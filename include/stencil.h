@@ -244,6 +244,19 @@ st_status stencil_batch_run(st_plan plan, int32_t n, void* const* grids, void* c
                             const double* coeffs, const int64_t* steps, void* stream);
 
 /*
+ * stencil_batch_run_flux -- stencil_batch_run that also adds each grid's
+ * outflow across the zero-rule boundary to flux[g] (device, n doubles), as
+ * stencil_run_flux does for one grid.  Radius-1 stars sum it inside the
+ * batch passes (one reduction launch per pass, fixed order); other patterns
+ * run grid by grid, one step per pass.  ST_PLAN_GRAPH is ignored (eager
+ * launches); the partial sums use a plan-owned buffer (the first call that
+ * needs it allocates).  Periodic batches leave flux untouched.
+ * Errors: as stencil_batch_run; ST_ERR_ARG for flux == NULL.
+ */
+st_status stencil_batch_run_flux(st_plan plan, int32_t n, void* const* grids, void* const* works,
+                                 const double* coeffs, const int64_t* steps, double* flux, void* stream);
+
+/*
  * stencil_run_ckpt -- variable-coefficient heat run with checkpoints (plan
  * made with ST_PLAN_VARCOEF: 3D radius-1 star, ST_BC_ZERO, FP64 or FP32).
  * The step is not in the paper; it is the conservative form of the explicit

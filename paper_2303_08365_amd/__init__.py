@@ -103,6 +103,7 @@ def library():
             "stencil_run_flux": [P, P, P, p_dbl, p_i64, i64, i32, P, P],
             "stencil_batch_plan": [ctypes.POINTER(P), ctypes.POINTER(_Pattern), i32, p_i64, i32, i32, u32],
             "stencil_batch_run": [P, i32, ctypes.POINTER(P), ctypes.POINTER(P), p_dbl, p_i64, P],
+            "stencil_batch_run_flux": [P, i32, ctypes.POINTER(P), ctypes.POINTER(P), p_dbl, p_i64, P, P],
             "stencil_run_ckpt": [P, P, P, P, ctypes.c_double, i64, i64, ctypes.POINTER(P), P],
             "stencil_adjoint_run": [P, P, ctypes.c_double, p_dbl, ctypes.POINTER(P), i64, i64, P, P, P,
                                     P, P],
@@ -328,7 +329,9 @@ class BatchPlan:
         _check(library().stencil_plan_select(self._h, int(kernel), int(tb), int(variant)))
         return self
 
-    def run(self, grids, works, coeffs, steps, stream=None):
+    def run(self, grids, works, coeffs, steps, stream=None, flux=None):
+        """``stencil_batch_run``; with `flux` (n doubles on the device)
+        ``stencil_batch_run_flux``, adding each grid's outflow to its entry."""
         n = len(self.shapes)
         if len(grids) != n or len(works) != n or len(coeffs) != n or len(steps) != n:
             raise ValueError("one grid, work buffer, coefficient row and step count per batch entry")
@@ -341,7 +344,13 @@ class BatchPlan:
         wp = (ctypes.c_void_p * n)(*[w.data_ptr() for w in works])
         cf = _doubles([c for row in coeffs for c in row])
         st = (ctypes.c_int64 * n)(*[int(s) for s in steps])
-        _check(library().stencil_batch_run(self._h, n, gp, wp, cf, st, _stream_handle(stream)))
+        if flux is None:
+            _check(library().stencil_batch_run(self._h, n, gp, wp, cf, st, _stream_handle(stream)))
+        else:
+            if flux.numel() != n or str(flux.dtype) != "torch.float64" or not flux.is_contiguous():
+                raise ValueError("flux must be a contiguous float64 device tensor with one entry per grid")
+            _check(library().stencil_batch_run_flux(self._h, n, gp, wp, cf, st, flux.data_ptr(),
+                                                    _stream_handle(stream)))
         return grids
 
 

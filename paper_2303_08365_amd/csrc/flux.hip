@@ -7,12 +7,14 @@
 // only within the pattern's reach of a face, so one step's outflow is a sum
 // over that band of the state the step reads.
 //
-// Two kernels:
+// Kernels:
 //   * flux_band_kernel: the band sum of one state, per work-group, for any
 //     point list (used when the steps run one per pass);
 //   * flux_reduce_kernel: adds the per-work-group (or per-wave) partial sums
 //     of one pass to the FP64 accumulator, in a fixed order, so the result
-//     does not depend on scheduling.
+//     does not depend on scheduling;
+//   * flux_reduce_batch_kernel: the same per grid of a batch pass, each grid's
+//     work items being a contiguous range of the partial sums.
 #include "dev_common.h"
 
 namespace st {
@@ -69,7 +71,26 @@ __global__ __launch_bounds__(kBlock) void flux_reduce_kernel(const double* part,
     if (threadIdx.x == 0) flux[0] += s;
 }
 
+__global__ __launch_bounds__(kBlock) void flux_reduce_batch_kernel(const Stream2DGrid* table, const double* part,
+                                                                     double* flux) {
+    __shared__ double red[kBlock];
+    const Stream2DGrid& d = table[blockIdx.x];
+    const int64_t begin = d.tile_begin, n = d.items;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) acc += part[begin + i];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) flux[d.gid] += s;
+}
+
 }  // namespace
+
+hipError_t launch_flux_reduce_batch(const Stream2DGrid* table, int count, const double* part, double* flux,
+                                    hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(flux_reduce_batch_kernel, dim3(static_cast<unsigned>(count)), dim3(kBlock), 0, s, table, part,
+                       flux);
+    return hipGetLastError();
+}
 
 hipError_t launch_flux_band(int dtype, const FluxBandArgs& a, double* part, int nblocks, hipStream_t s) {
     if (nblocks < 1) return hipErrorInvalidValue;

@@ -45,6 +45,8 @@ struct Stream2DGrid {
     int32_t vec_ok;      // rows and base are aligned for whole-vector access
     int32_t tb;          // fused steps this pass (<= template depth)
     int64_t tile_begin;  // first work item of this grid in the batch
+    int64_t items;       // work items of this grid (outflow reduction)
+    int32_t gid;         // batch entry the descriptor belongs to (outflow reduction)
     double w[32];        // canonical-order weights
 };
 struct Stream2DArgs {
@@ -167,6 +169,10 @@ constexpr int kFluxBandBlocks = 512;
 hipError_t launch_flux_band(int dtype, const FluxBandArgs& a, double* part, int nblocks, hipStream_t s);
 // flux[0] += sum of part[0 .. n) (one work-group, fixed order)
 hipError_t launch_flux_reduce(const double* part, int64_t n, double* flux, hipStream_t s);
+// batch: for each of the `count` descriptors of a pass, flux[gid] += sum of
+// part[tile_begin .. tile_begin + items) (one work-group per descriptor)
+hipError_t launch_flux_reduce_batch(const struct Stream2DGrid* table, int count, const double* part, double* flux,
+                                    hipStream_t s);
 
 // plain streaming copy (bandwidth reference); 16-byte aligned buffers
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes, int cus, hipStream_t s);

@@ -1344,6 +1344,8 @@ st_status batch_prepare(st_plan_s* plan, const Candidate& c, int32_t n, void* co
             G.vec_ok = (G.nx % c.k2.vx == 0) && aligned16(grids[g]) && aligned16(works[g]);
             G.tb = tb;
             G.tile_begin = begin;
+            G.items = geo.items;
+            G.gid = g;
             canonical_weights(plan, coeffs + static_cast<int64_t>(g) * plan->npoints, G.w);
             begin += geo.items;
             table.push_back(G);
@@ -1377,17 +1379,30 @@ st_status batch_prepare(st_plan_s* plan, const Candidate& c, int32_t n, void* co
     return ST_OK;
 }
 
+// With `flux` (one device double per grid), every pass runs the
+// outflow-summing twin and a per-grid reduction of its partial sums.
 st_status batch_launches(const st_plan_s* plan, const Candidate& c, const std::vector<BatchLaunch>& launches,
-                         const std::vector<int>& copies, void* const* grids, void* const* works, hipStream_t s) {
+                         const std::vector<int>& copies, void* const* grids, void* const* works, hipStream_t s,
+                         double* flux = nullptr) {
     const Stream2DGrid* dev = static_cast<const Stream2DGrid*>(plan->table_dev);
+    Stream2DKey key = c.k2;
+    if (flux) {
+        key.flux = 1;
+        if (!stream2d_has(key)) key.tbmax = 8;
+    }
     for (const BatchLaunch& L : launches) {
         Stream2DArgs a;
         std::memset(&a, 0, sizeof(a));
         a.grids = dev + L.first;
         a.ngrids = L.count;
         a.items = L.items;
-        const hipError_t e = launch_stream2d(c.k2, a, s);
+        a.flux_part = flux ? plan->flux_part : nullptr;
+        const hipError_t e = launch_stream2d(key, a, s);
         if (e != hipSuccess) return hip_fail(e, "stream2d batch launch");
+        if (flux) {
+            const hipError_t r = launch_flux_reduce_batch(dev + L.first, L.count, plan->flux_part, flux, s);
+            if (r != hipSuccess) return hip_fail(r, "outflow batch reduce launch");
+        }
     }
     for (int g : copies) {
         const size_t bytes = static_cast<size_t>(plan->grids[g].ny * plan->grids[g].nx) * elem_bytes(plan->dtype);
@@ -1397,10 +1412,12 @@ st_status batch_launches(const st_plan_s* plan, const Candidate& c, const std::v
 }
 
 st_status batch_run_impl(st_plan_s* plan, int32_t n, void* const* grids, void* const* works, const double* coeffs,
-                         const int64_t* steps, hipStream_t s) {
+                         const int64_t* steps, hipStream_t s, double* flux = nullptr) {
     const Candidate c = plan->cands[plan->sel];
-    if (c.kernel == ST_KERNEL_NAIVE) {
-        // pattern without a fused family: grid by grid
+    if (flux && plan->bc != kZero) flux = nullptr;  // a periodic grid has no boundary
+    if (c.kernel == ST_KERNEL_NAIVE || (flux && !flux_fused(plan, c))) {
+        // pattern without a fused family, or outflow without a summing twin:
+        // grid by grid
         st_plan_s one;
         one.ndim = plan->ndim;
         one.dtype = plan->dtype;
@@ -1414,9 +1431,35 @@ st_status batch_run_impl(st_plan_s* plan, int32_t n, void* const* grids, void* c
             one.n[2] = plan->grids[g].nx;
             double w[kMaxPoints];
             canonical_weights(plan, coeffs + static_cast<int64_t>(g) * plan->npoints, w);
-            if (st_status r = run_steps(&one, c, grids[g], works[g], w, steps[g], s); r != ST_OK) return r;
+            // the outflow partial sums live in the batch plan's buffer
+            one.flux_part = plan->flux_part;
+            one.flux_cap = plan->flux_cap;
+            const st_status r = run_steps(&one, c, grids[g], works[g], w, steps[g], s, flux ? flux + g : nullptr);
+            plan->flux_part = one.flux_part;
+            plan->flux_cap = one.flux_cap;
+            one.flux_part = nullptr;
+            if (r != ST_OK) return r;
         }
         return ST_OK;
+    }
+    if (flux) {
+        // eager launches (no graph): the passes with their per-grid reductions
+        std::vector<uint64_t> key;
+        key_push(key, static_cast<int64_t>(plan->sel));
+        for (int g = 0; g < n; ++g) {
+            key_push(key, grids[g]);
+            key_push(key, works[g]);
+            key_push(key, steps[g]);
+            for (int i = 0; i < plan->npoints; ++i) key_push(key, coeffs[static_cast<int64_t>(g) * plan->npoints + i]);
+        }
+        std::vector<BatchLaunch> launches;
+        std::vector<int> copies;
+        if (st_status r = batch_prepare(plan, c, n, grids, works, coeffs, steps, key, s, launches, copies); r != ST_OK)
+            return r;
+        int64_t need = 1;
+        for (const BatchLaunch& L : launches) need = std::max(need, L.items);
+        if (st_status r = ensure_flux_parts(plan, need, s); r != ST_OK) return r;
+        return batch_launches(plan, c, launches, copies, grids, works, s, flux);
     }
     std::vector<uint64_t> key;
     key_push(key, static_cast<int64_t>(plan->sel));
@@ -1441,8 +1484,9 @@ st_status batch_run_impl(st_plan_s* plan, int32_t n, void* const* grids, void* c
 
 }  // namespace
 
-extern "C" st_status stencil_batch_run(st_plan plan, int32_t n, void* const* grids, void* const* works,
-                                       const double* coeffs, const int64_t* steps, void* stream) {
+namespace {
+st_status batch_entry(st_plan plan, int32_t n, void* const* grids, void* const* works, const double* coeffs,
+                      const int64_t* steps, void* stream, double* flux) {
     if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
     if (!plan->batch) return fail(ST_ERR_MISMATCH, "single-grid plan passed to stencil_batch_run");
     if (n != static_cast<int32_t>(plan->grids.size()))
@@ -1460,7 +1504,19 @@ extern "C" st_status stencil_batch_run(st_plan plan, int32_t n, void* const* gri
     }
     if (maxsteps == 0) return ST_OK;
     if (st_status r = need_device(); r != ST_OK) return r;
-    return batch_run_impl(plan, n, grids, works, coeffs, steps, static_cast<hipStream_t>(stream));
+    return batch_run_impl(plan, n, grids, works, coeffs, steps, static_cast<hipStream_t>(stream), flux);
+}
+}  // namespace
+
+extern "C" st_status stencil_batch_run(st_plan plan, int32_t n, void* const* grids, void* const* works,
+                                       const double* coeffs, const int64_t* steps, void* stream) {
+    return batch_entry(plan, n, grids, works, coeffs, steps, stream, nullptr);
+}
+
+extern "C" st_status stencil_batch_run_flux(st_plan plan, int32_t n, void* const* grids, void* const* works,
+                                            const double* coeffs, const int64_t* steps, double* flux, void* stream) {
+    if (!flux) return fail(ST_ERR_ARG, "flux is NULL");
+    return batch_entry(plan, n, grids, works, coeffs, steps, stream, flux);
 }
 
 namespace {

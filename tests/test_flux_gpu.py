@@ -166,3 +166,48 @@ def test_heat3d_512_total_plus_outflow_is_conserved(dtype):
           flush=True)
     assert out > 0
     assert drift <= (1e-13 if dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("dtype,kind", [("f64", "star"), ("f32", "star"), ("f64", "box"), ("bf16", "star")])
+def test_batch_outflow_matches_oracle_per_grid(dtype, kind):
+    import torch
+    import paper_2303_08365_amd as st
+    offs = synth.star_offsets(2, 1) if kind == "star" else synth.box_offsets(2, 1)
+    shapes = [(40, 300), (129, 77), (256, 516), (33, 1030)]
+    steps = [9, 4, 13, 6] if dtype != "bf16" else [4, 3, 5, 2]
+    wdt = "f64" if dtype == "f64" else "f32"
+    rng = np.random.default_rng(61)
+    coeffs = []
+    for _ in shapes:
+        r = rng.uniform(0.2, 1.0, len(offs))
+        coeffs.append(list(synth.adjust_centre(r / r.sum(), wdt)))
+    u0s = [synth.uniform_field(sh, seed=62 + i) for i, sh in enumerate(shapes)]
+    plan = st.BatchPlan(offs, shapes, dtype, "zero")
+    print(f"batch flux {dtype} {kind} plan {plan.info()}", flush=True)
+    grids = [to_device(u, dtype) for u in u0s]
+    works = [torch.empty_like(g) for g in grids]
+    flux = torch.full((len(shapes),), 0.5, dtype=torch.float64, device="cuda")
+    plan.run(grids, works, coeffs, steps, flux=flux)
+    out = flux.cpu().numpy() - 0.5
+    plain = [to_device(u, dtype) for u in u0s]
+    plan.run(plain, works, coeffs, steps)
+    for g, (u0, w, t, got_g, pl) in enumerate(zip(u0s, coeffs, steps, grids, plain)):
+        ref, rout = _ref_flux(u0, offs, w, t, dtype)
+        h = to_host(got_g)
+        check(h, ref, dtype, t, f"grid {g}")
+        assert np.array_equal(h, to_host(pl)), g
+        tol = _flux_tol(offs, w, u0.shape, t, dtype, u0)
+        _close(out[g], rout, tol, dtype, f"batch grid {g}")
+
+
+def test_batch_outflow_periodic_untouched():
+    import torch
+    import paper_2303_08365_amd as st
+    offs = synth.star_offsets(2, 1)
+    shapes = [(40, 300), (64, 64)]
+    plan = st.BatchPlan(offs, shapes, "f64", "periodic")
+    grids = [to_device(synth.uniform_field(sh, seed=70), "f64") for sh in shapes]
+    works = [torch.empty_like(g) for g in grids]
+    flux = torch.full((2,), 1.25, dtype=torch.float64, device="cuda")
+    plan.run(grids, works, [list(synth.heat_weights(2, 0.2))] * 2, [5, 5], flux=flux)
+    assert np.array_equal(flux.cpu().numpy(), np.array([1.25, 1.25]))
