@@ -186,6 +186,40 @@ def test_impulse_response_2d_box_is_separable():
     assert np.max(np.abs(out - np.outer(row, row))) < 1e-15
 
 
+def test_impulse_response_3d_box_and_1d_star_closed_forms():
+    # 3D box 1/27 = (1/3)^3 per axis: the impulse spreads as the product of
+    # three trinomial rows; a 1D 5-point star with weights 1/5 spreads as the
+    # pentanomial coefficients (coefficients of (1 + x + ... + x^4)^T) / 5^T
+    T, n = 4, 16
+
+    def trinomial_row():
+        row = np.zeros(n)
+        for m in range(-T, T + 1):
+            tot = 0
+            for nm in range(T + 1):
+                npl = nm - m
+                n0 = T - nm - npl
+                if npl >= 0 and n0 >= 0:
+                    tot += math.factorial(T) // (math.factorial(nm) * math.factorial(n0) * math.factorial(npl))
+            row[m % n] = tot / 3.0 ** T
+        return row
+
+    u0 = np.zeros((n, n, n))
+    u0[0, 0, 0] = 1.0
+    out = oracle.sweep(u0, synth.box_offsets(3, 1), np.full(27, 1.0 / 27.0), T, bc="periodic")
+    r = trinomial_row()
+    assert np.max(np.abs(out - np.einsum("i,j,k->ijk", r, r, r))) < 1e-15
+    poly = np.array([1.0])
+    for _ in range(T):
+        poly = np.convolve(poly, np.ones(5))
+    u1 = np.zeros(64)
+    u1[20] = 1.0
+    out1 = oracle.sweep(u1, synth.star_offsets(1, 2), np.full(5, 0.2), T, bc="zero")
+    ref1 = np.zeros(64)
+    ref1[20 - 2 * T:20 + 2 * T + 1] = poly / 5.0 ** T
+    assert np.max(np.abs(out1 - ref1)) < 1e-15
+
+
 # --------------------------------------------------------------------------
 # conservation, maximum principle, identities
 # --------------------------------------------------------------------------
