@@ -94,7 +94,8 @@ def test_fused_and_one_step_outflow_agree(dtype, shape):
 @pytest.mark.parametrize("dtype,kind,r,shape", [
     ("f64", "star", 1, (512, 512)), ("f32", "box", 1, (130, 301)), ("f64", "star", 2, (67, 90)),
     ("f32", "star", 2, (14, 23, 40)), ("f64", "box", 1, (9, 12, 17)), ("bf16", "star", 1, (100, 260)),
-    ("f64", "star", 3, (41,)),
+    ("f64", "star", 3, (41,)), ("f64", "star", 1, (5000,)), ("f32", "star", 2, (3001,)),
+    ("f64", "box", 1, (20, 33, 300)),
 ])
 def test_other_patterns_outflow_matches_oracle(dtype, kind, r, shape):
     import paper_2303_08365_amd as st
