@@ -346,6 +346,41 @@ def test_varcoef_adjoint_matches_finite_differences():
     assert oracle.rel_l2(gk, fd_k) < 1e-7
 
 
+def _golden_varcoef(golden_dir):
+    vals = {}
+    with open(os.path.join(golden_dir, "varcoef_1x2x3.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            q, y, x, num, den = line.split()
+            vals.setdefault(q, np.zeros((1, 2, 3)))[0, int(y), int(x)] = float(Fraction(int(num), int(den)))
+    return vals
+
+
+_VC_K = np.array([[[1.0, 2.0, 3.0], [4.0, 5.0, 6.0]]])
+_VC_U0 = np.array([[[3.0, 1.0, 2.0], [0.0, 2.0, 4.0]]])
+
+
+def test_varcoef_golden_steps_pin_the_face_average(golden_dir):
+    # hand-evaluated non-uniform k: a face mean other than the arithmetic one
+    # (geometric, harmonic) or a dropped edge face changes these values
+    g = _golden_varcoef(golden_dir)
+    for steps, q in ((1, "u1"), (2, "u2")):
+        got = oracle.varcoef_forward(_VC_U0, _VC_K, 0.1, steps)
+        assert np.allclose(got, g[q], rtol=4e-15, atol=4e-15), (steps, got, g[q])
+
+
+def test_varcoef_golden_gradient_pins_the_half_split(golden_dir):
+    # one step, L = u1(0,1): dL/dk gives each interior face's derivative half
+    # to either cell; dL/du0 carries the face means themselves
+    g = _golden_varcoef(golden_dir)
+    lam = np.zeros((1, 2, 3))
+    lam[0, 0, 1] = 1.0
+    gu, gk = oracle.varcoef_adjoint(_VC_U0, _VC_K, 0.1, 1, lam)
+    assert np.allclose(gk, g["gk"], rtol=4e-15, atol=4e-16), gk
+    assert np.allclose(gu, g["gu"], rtol=4e-15, atol=4e-16), gu
+
+
 def test_varcoef_operator_is_symmetric():
     # one step is u -> A u with A symmetric: the scatter adjoint of one step
     # applied to v equals the forward step applied to v (no gk).
