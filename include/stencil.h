@@ -55,7 +55,8 @@ typedef enum {
     ST_ERR_MISMATCH = -3,     /* shape/boundary/count differs from the plan     */
     ST_ERR_NOMEM = -4,        /* host or device allocation failed               */
     ST_ERR_HIP = -5,          /* a HIP runtime call failed (see last_error)     */
-    ST_ERR_CAPTURE = -6       /* an allocating call made during stream capture  */
+    ST_ERR_CAPTURE = -6       /* reserved: no call returns it (run calls do not */
+                              /* allocate; the value keeps its number)         */
 } st_status;
 
 typedef enum { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 } st_dtype;   /* storage type */
@@ -71,6 +72,9 @@ typedef enum { ST_BC_ZERO = 0, ST_BC_PERIODIC = 1 } st_boundary;
 #define ST_PLAN_VARCOEF 0x4u   /* variable-coefficient heat operator (3D,      */
                                /* radius-1 star, ST_BC_ZERO, FP64/FP32 only);  */
                                /* run with stencil_run_ckpt                    */
+#define ST_PLAN_OWN_WORK 0x10u /* the plan allocates a work buffer of the      */
+                               /* grid's size now; stencil_run / _flux then    */
+                               /* accept work == NULL (single-grid plans)      */
 
 typedef struct {
     int32_t ndim;             /* 1..3                                          */
@@ -105,6 +109,16 @@ typedef struct {
  * stencil_plan -- choose kernel, tile, fused depth and launch geometry for
  * one grid shape (paper Sec. 5.2: the scheduler is fixed from a profile of the
  * problem; Tab. 1 lists the blocking sizes per benchmark).
+ *
+ * Allocation.  Every device buffer a plan owns is allocated here, on the
+ * current device: the outflow partial sums (zero rule), the work buffer
+ * (ST_PLAN_OWN_WORK), the batch descriptor table, the capture stream
+ * (ST_PLAN_GRAPH), and the plan of the transposed sweep used by
+ * stencil_adjoint_run.  No run call allocates device or pinned memory or
+ * waits for the device; the one exception is ST_PLAN_GRAPH, whose first run
+ * with a new argument set captures and instantiates a graph.  A plan made
+ * where no device is present can describe its tilings, but its run calls
+ * fail with ST_ERR_HIP.
  *   out      receives the plan; *out is NULL on failure.
  *   pattern  point list (copied).  Points are evaluated in a canonical order
  *            (centre, then lexicographic by offset) by every kernel, so all
@@ -165,10 +179,12 @@ st_status stencil_plan_select(st_plan plan, int32_t kernel, int32_t tb, int32_t 
 
 /*
  * stencil_run -- run `steps` steps on one grid (Alg. 1 with T = steps).
+ *   plan    required: the call carries no pattern, so a NULL plan could not
+ *           say which stencil to apply (ST_ERR_ARG).
  *   grid    device, in: u_0, out: u_T; plan->shape cells of the storage type.
- *   work    device buffer of the same size, clobbered; NULL makes the plan
- *           allocate and keep one on first use (that first call allocates
- *           and is then not capturable into a HIP graph).
+ *   work    device buffer of the same size, clobbered; NULL uses the plan's
+ *           own buffer (plans made with ST_PLAN_OWN_WORK; ST_ERR_ARG
+ *           otherwise).
  *   coeffs  host FP64 weights, one per pattern point, caller's order.
  *   shape   must equal the plan's shape (ST_ERR_MISMATCH otherwise).
  *   bc      must equal the plan's boundary (ST_ERR_MISMATCH otherwise).
@@ -197,9 +213,9 @@ st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs
  *   other arguments as for stencil_run; the grid ends bit-identical to
  *           stencil_run's.
  * The sum is deterministic: partial sums go to a plan-owned device buffer
- * (allocated by the first call that needs it, which is then not capturable)
- * and one work-group adds them in a fixed order.  That buffer belongs to the
- * plan, so calls on one plan must not overlap on different streams.  The fused 3D radius-1
+ * (allocated with the plan) and one work-group adds them in a fixed order.
+ * That buffer belongs to the plan, so calls on one plan must not overlap on
+ * different streams.  The fused 3D radius-1
  * kernels (FP64, FP32, bfloat16 default tilings) sum the outflow inside
  * their passes; every other plan runs one step per pass with a band kernel
  * over the state each step reads.  ST_PLAN_GRAPH is ignored here (the
@@ -228,16 +244,20 @@ st_status stencil_batch_plan(st_plan* out, const st_pattern* pattern, int32_t n,
                              uint32_t flags);
 
 /*
- * stencil_batch_run -- run grid g for steps[g] steps, for every g, in
- * ceil(max steps / tb) launches on `stream`.
+ * stencil_batch_run -- run grid g for steps[g] steps, for every g, in about
+ * ceil(max steps / tb) launches on `stream` (each launch covers every grid;
+ * grid g runs the passes of its own step count, the grids with fewer passes
+ * idle in the last launches).
  *   grids, works  host arrays of n device pointers (work buffers as in
  *                 stencil_run, required here).
  *   coeffs        host FP64, n * npoints, row g holds grid g's weights.
  *   steps         host, n step counts (each >= 0).
- * Results land in grids[g].  The plan uploads a descriptor table through a
- * plan-owned pinned buffer whenever the arguments differ from the previous
- * call's (waiting, if needed, for the previous upload to finish reading it);
- * repeated calls with the same arguments reuse the device table.
+ * Results land in grids[g].  The plan's device descriptor table (one entry
+ * per grid, allocated with the plan) is rewritten in stream order whenever
+ * the arguments differ from what it holds: the entries travel as kernel
+ * arguments, so the call neither allocates nor waits, and a graph that
+ * captures the call records the table it needs and rewrites it on every
+ * replay.  Calls on one plan must not overlap on different streams.
  * Errors: ST_ERR_ARG, ST_ERR_MISMATCH (n differs from the plan), ST_ERR_HIP.
  */
 st_status stencil_batch_run(st_plan plan, int32_t n, void* const* grids, void* const* works,
@@ -249,8 +269,8 @@ st_status stencil_batch_run(st_plan plan, int32_t n, void* const* grids, void* c
  * stencil_run_flux does for one grid.  Radius-1 stars sum it inside the
  * batch passes (one reduction launch per pass, fixed order); other patterns
  * run grid by grid, one step per pass.  ST_PLAN_GRAPH is ignored (eager
- * launches); the partial sums use a plan-owned buffer (the first call that
- * needs it allocates).  Periodic batches leave flux untouched.
+ * launches); the partial sums use a plan-owned buffer allocated with the
+ * plan.  Periodic batches leave flux untouched.
  * Errors: as stencil_batch_run; ST_ERR_ARG for flux == NULL.
  */
 st_status stencil_batch_run_flux(st_plan plan, int32_t n, void* const* grids, void* const* works,
@@ -277,8 +297,10 @@ st_status stencil_run_ckpt(st_plan plan, void* grid, void* work, const void* k, 
  * stencil_adjoint_run -- reverse-mode sweep: lambda holds dL/du^steps on
  * entry and dL/du^0 on exit.
  *   Constant-weight plan: k, grad_k NULL; coeffs as for stencil_run; runs
- *     the transposed stencil (every offset negated, same boundary) `steps`
- *     times; ckpts, every and seg are ignored.
+ *     the transpose of Alg. 1's update (Sec. 2.1): u -> sum_p w_p u(x + o_p)
+ *     is linear, and its transpose is the same sweep with every offset
+ *     negated under the same boundary rule (planned with the plan), applied
+ *     `steps` times; ckpts, every and seg are ignored.
  *   Variable-coefficient plan: coeffs ignored; k and alpha as in the forward
  *     run; ckpts / every as stored by stencil_run_ckpt.  Each checkpoint
  *     segment is recomputed forward into `seg` (min(every, steps) - 1

@@ -18,7 +18,7 @@ from typing import Iterable, List, Optional, Sequence
 __all__ = [
     "StencilError", "Plan", "BatchPlan", "run", "library", "library_path", "build",
     "F64", "F32", "BF16", "BC_ZERO", "BC_PERIODIC", "PLAN_AUTOTUNE", "PLAN_NAIVE",
-    "PLAN_VARCOEF", "PLAN_GRAPH", "KERNEL_NAIVE", "KERNEL_STREAM2D", "KERNEL_STREAM3D", "KERNEL_VARCOEF3D",
+    "PLAN_VARCOEF", "PLAN_GRAPH", "PLAN_OWN_WORK", "KERNEL_NAIVE", "KERNEL_STREAM2D", "KERNEL_STREAM3D", "KERNEL_VARCOEF3D",
     "KERNEL_STREAM1D", "KERNEL_BOX3D",
     "STATUS", "StencilFn", "varcoef_plan", "copy", "autotune_cache", "batch_run",
 ]
@@ -28,7 +28,7 @@ _LIB_PATH = os.path.join(_HERE, "libstencil.so")
 
 F64, F32, BF16 = 0, 1, 2
 BC_ZERO, BC_PERIODIC = 0, 1
-PLAN_AUTOTUNE, PLAN_NAIVE, PLAN_VARCOEF, PLAN_GRAPH = 0x1, 0x2, 0x4, 0x8
+PLAN_AUTOTUNE, PLAN_NAIVE, PLAN_VARCOEF, PLAN_GRAPH, PLAN_OWN_WORK = 0x1, 0x2, 0x4, 0x8, 0x10
 KERNEL_NAIVE, KERNEL_STREAM2D, KERNEL_STREAM3D, KERNEL_VARCOEF3D, KERNEL_STREAM1D, KERNEL_BOX3D = 0, 1, 2, 3, 4, 5
 STATUS = {0: "ST_OK", -1: "ST_ERR_ARG", -2: "ST_ERR_UNSUPPORTED", -3: "ST_ERR_MISMATCH",
           -4: "ST_ERR_NOMEM", -5: "ST_ERR_HIP", -6: "ST_ERR_CAPTURE"}
@@ -160,18 +160,38 @@ def _tensor_dtype(t) -> int:
     return m[t.dtype]
 
 
+def _on_one_gpu(*named):
+    """Every tensor the kernels will read or write must be GPU memory of one
+    device: a host pointer handed to a kernel would fault the GPU (no XNACK).
+    `named` holds (tensor or None, what) pairs; None entries are skipped."""
+    dev = None
+    for t, what in named:
+        if t is None:
+            continue
+        if not getattr(t, "is_cuda", False):
+            raise ValueError(f"{what} must be a GPU tensor (got device {getattr(t, 'device', '?')})")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise ValueError(f"{what} is on {t.device}, the other tensors on {dev}")
+    return dev
+
+
 class Plan:
     """A plan for one grid shape (``stencil_plan``)."""
 
     def __init__(self, offsets, shape, dtype="f64", bc="zero", autotune=False, naive=False,
-                 varcoef=False, graph=False):
+                 varcoef=False, graph=False, own_work=False):
         lib = library()
         self.offsets = [tuple(int(v) for v in o) for o in offsets]
         self.shape = tuple(int(s) for s in shape)
         self.dtype = _DTYPES[dtype]
         self.bc = _BCS[bc]
+        self.own_work = bool(own_work)
+        self._work = None
         flags = ((PLAN_AUTOTUNE if autotune else 0) | (PLAN_NAIVE if naive else 0) |
-                 (PLAN_VARCOEF if varcoef else 0) | (PLAN_GRAPH if graph else 0))
+                 (PLAN_VARCOEF if varcoef else 0) | (PLAN_GRAPH if graph else 0) |
+                 (PLAN_OWN_WORK if own_work else 0))
         pat, self._flat = _pattern(self.offsets)
         shp = (ctypes.c_int64 * len(self.shape))(*self.shape)
         h = ctypes.c_void_p()
@@ -215,6 +235,8 @@ class Plan:
             raise ValueError("grid must be a contiguous tensor of the plan's dtype")
         if work is not None and (work.numel() != grid.numel() or work.dtype != grid.dtype):
             raise ValueError("work must match grid in size and dtype")
+        _on_one_gpu((grid, "grid"), (work, "work"))
+        work = self._work_for(grid, work)
         w = _doubles(coeffs)
         if len(w) != len(self.offsets):
             raise ValueError("one coefficient per point")
@@ -236,6 +258,8 @@ class Plan:
             raise ValueError("work must match grid in size and dtype")
         if flux.numel() != 1 or str(flux.dtype) != "torch.float64" or flux.device != grid.device:
             raise ValueError("flux must be a one-element float64 tensor on the grid's device")
+        _on_one_gpu((grid, "grid"), (work, "work"), (flux, "flux"))
+        work = self._work_for(grid, work)
         w = _doubles(coeffs)
         if len(w) != len(self.offsets):
             raise ValueError("one coefficient per point")
@@ -244,6 +268,16 @@ class Plan:
                                           work.data_ptr() if work is not None else None, w, shp,
                                           int(steps), self.bc, flux.data_ptr(), _stream_handle(stream)))
         return grid
+
+    def _work_for(self, grid, work):
+        """The work buffer to pass: the caller's, NULL for a plan that owns
+        one, or a torch tensor this object keeps for later calls."""
+        if work is not None or self.own_work:
+            return work
+        if self._work is None or self._work.device != grid.device:
+            import torch
+            self._work = torch.empty_like(grid)
+        return self._work
 
     def _same(self, t, what):
         if tuple(t.shape) != self.shape or not t.is_contiguous() or _tensor_dtype(t) != self.dtype:
@@ -258,14 +292,19 @@ class Plan:
         self._same(grid, "grid")
         self._same(k, "k")
         self._same(work, "work")
+        if int(every) < 0:
+            raise ValueError("every must be >= 0")
         cp = None
+        need = 0
         if every:
             need = -(-int(steps) // int(every))
             if ckpts is None or len(ckpts) < need:
                 raise ValueError(f"{need} checkpoint tensors are required")
             for c in ckpts[:need]:
                 self._same(c, "checkpoint")
-            cp = (ctypes.c_void_p * need)(*[c.data_ptr() for c in ckpts[:need]])
+            cp = (ctypes.c_void_p * max(need, 1))(*[c.data_ptr() for c in ckpts[:need]])
+        _on_one_gpu((grid, "grid"), (k, "k"), (work, "work"),
+                    *[(c, "checkpoint") for c in (ckpts or [])[:need]])
         _check(library().stencil_run_ckpt(self._h, grid.data_ptr(), work.data_ptr(), k.data_ptr(),
                                           float(alpha), int(steps), int(every), cp,
                                           _stream_handle(stream)))
@@ -276,14 +315,39 @@ class Plan:
         """Reverse sweep (``stencil_adjoint_run``): `lam` goes from dL/du_T to dL/du_0."""
         self._same(lam, "lambda")
         self._same(work, "work")
-        w = _doubles(coeffs) if coeffs is not None else None
+        steps, every = int(steps), int(every)
+        w = None
+        if coeffs is not None:
+            w = _doubles(coeffs)
+            if len(w) != len(self.offsets):
+                raise ValueError("one coefficient per point")
+        if k is not None:
+            self._same(k, "k")
         cp = None
-        if ckpts is not None:
-            cp = (ctypes.c_void_p * len(ckpts))(*[c.data_ptr() for c in ckpts])
+        need = 0
+        if k is not None and steps > 0:
+            # variable coefficients: ceil(steps/every) checkpoints of the
+            # grid's shape and min(every, steps) - 1 recomputed states in seg
+            if every < 1:
+                raise ValueError("every must be >= 1 with variable coefficients")
+            need = -(-steps // every)
+            if ckpts is None or len(ckpts) < need:
+                raise ValueError(f"{need} checkpoint tensors are required")
+            for c in ckpts[:need]:
+                self._same(c, "checkpoint")
+            cp = (ctypes.c_void_p * need)(*[c.data_ptr() for c in ckpts[:need]])
+            nseg = min(every, steps) - 1
+            if nseg > 0:
+                if seg is None:
+                    raise ValueError(f"seg must hold {nseg} states of the grid's shape")
+                if not seg.is_contiguous() or _tensor_dtype(seg) != self.dtype:
+                    raise ValueError("seg must be contiguous and of the plan's dtype")
+                if seg.numel() < nseg * lam.numel():
+                    raise ValueError(f"seg holds {seg.numel()} values, {nseg} states need {nseg * lam.numel()}")
         if grad_k is not None:
             self._same(grad_k, "grad_k")
-        if seg is not None and (not seg.is_contiguous() or seg.dtype != lam.dtype):
-            raise ValueError("seg must be contiguous and of the plan's dtype")
+        _on_one_gpu((lam, "lambda"), (work, "work"), (k, "k"), (grad_k, "grad_k"),
+                    (seg if need else None, "seg"), *[(c, "checkpoint") for c in (ckpts or [])[:need]])
         _check(library().stencil_adjoint_run(
             self._h, k.data_ptr() if k is not None else None, float(alpha), w, cp, int(every),
             int(steps), lam.data_ptr(), grad_k.data_ptr() if grad_k is not None else None,
@@ -340,6 +404,8 @@ class BatchPlan:
                 raise ValueError("grid shape/dtype/contiguity differs from the plan")
             if w.numel() != g.numel() or w.dtype != g.dtype:
                 raise ValueError("work must match its grid")
+        _on_one_gpu(*[(g, f"grid {i}") for i, g in enumerate(grids)],
+                    *[(w, f"work {i}") for i, w in enumerate(works)], (flux, "flux"))
         gp = (ctypes.c_void_p * n)(*[g.data_ptr() for g in grids])
         wp = (ctypes.c_void_p * n)(*[w.data_ptr() for w in works])
         cf = _doubles([c for row in coeffs for c in row])
@@ -365,6 +431,7 @@ def copy(dst, src, stream=None):
     nbytes = src.numel() * src.element_size()
     if dst.numel() * dst.element_size() != nbytes:
         raise ValueError("dst and src differ in size")
+    _on_one_gpu((dst, "dst"), (src, "src"))
     _check(library().stencil_copy(dst.data_ptr(), src.data_ptr(), nbytes, _stream_handle(stream)))
     return dst
 

@@ -53,4 +53,34 @@ hipError_t launch_copy(void* dst, const void* src, int64_t bytes, int cus, hipSt
     return hipGetLastError();
 }
 
+// Stream-ordered upload of a small host table: each launch carries up to
+// kTableWords 32-bit words in its argument block, so the runtime copies them
+// when the launch is enqueued (or recorded into a graph) and the caller's
+// host buffer is free at once -- no pinned staging buffer, no event to wait
+// for, and a captured graph keeps its own copy of the table.
+constexpr int kTableWords = 512;
+struct TableChunk {
+    uint32_t words[kTableWords];
+};
+
+__global__ __launch_bounds__(256) void table_write_kernel(uint32_t* dst, uint32_t nwords, const TableChunk c) {
+    for (uint32_t i = threadIdx.x; i < nwords; i += 256) dst[i] = c.words[i];
+}
+
+hipError_t launch_table_write(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if ((bytes & 3u) != 0 || (reinterpret_cast<uintptr_t>(dst) & 3u) != 0) return hipErrorInvalidValue;
+    const size_t words = bytes / 4;
+    const unsigned char* from = static_cast<const unsigned char*>(src);
+    for (size_t w0 = 0; w0 < words; w0 += kTableWords) {
+        const size_t n = words - w0 < static_cast<size_t>(kTableWords) ? words - w0 : kTableWords;
+        TableChunk c;
+        __builtin_memcpy(c.words, from + 4 * w0, 4 * n);
+        hipLaunchKernelGGL(table_write_kernel, dim3(1), dim3(256), 0, s, static_cast<uint32_t*>(dst) + w0,
+                           static_cast<uint32_t>(n), c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace st

@@ -43,7 +43,9 @@ struct Stream2DGrid {
     int32_t out_w;       // output columns per strip = 64*VX - 2*hxa
     int32_t hxa;         // redundant halo columns each side (multiple of VX)
     int32_t vec_ok;      // rows and base are aligned for whole-vector access
-    int32_t tb;          // fused steps this pass (<= template depth)
+    int32_t tb;          // fused steps this pass (<= template depth); batch: the full depth
+    int32_t full;        // batch: passes of depth tb, then up to 3 tail passes
+    int32_t tail[3];     // batch: depths of the tail passes (0 = no such pass)
     int64_t tile_begin;  // first work item of this grid in the batch
     int64_t items;       // work items of this grid (outflow reduction)
     int32_t gid;         // batch entry the descriptor belongs to (outflow reduction)
@@ -53,8 +55,10 @@ struct Stream2DArgs {
     const Stream2DGrid* grids;  // device table (batch) or nullptr
     Stream2DGrid one;           // used when grids == nullptr
     int32_t ngrids;
+    int32_t pass;               // batch: pass index (odd passes read dst and write src;
+                                // a grid whose schedule has no such pass does nothing)
     int64_t items;              // total (grid, strip, chunk) work items
-    double* flux_part;          // outflow variants (single grid): one partial sum per work item
+    double* flux_part;          // outflow variants: one partial sum per work item
 };
 // Instantiation key for the 2D family.
 struct Stream2DKey {
@@ -176,5 +180,9 @@ hipError_t launch_flux_reduce_batch(const struct Stream2DGrid* table, int count,
 
 // plain streaming copy (bandwidth reference); 16-byte aligned buffers
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes, int cus, hipStream_t s);
+// writes `bytes` host bytes to device memory `dst` in stream order: the bytes
+// travel as kernel arguments (captured with the launch), so the host buffer
+// may be reused at once and nothing waits; dst 4-byte aligned, bytes % 4 == 0
+hipError_t launch_table_write(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 }  // namespace st

@@ -177,26 +177,24 @@ struct st_plan_s {
     int32_t cls = kGeneral;
     std::vector<Candidate> cands;
     int32_t sel = 0;
-    void* owned_work = nullptr;
-    size_t owned_bytes = 0;
-    // outflow runs: partial sums of one pass (per wave or per work-group)
+    // Device memory a plan owns is allocated when the plan is made (see
+    // plan_buffers), never by a run call.
+    void* owned_work = nullptr;   // ST_PLAN_OWN_WORK
+    // outflow runs (zero rule): partial sums of one pass (per wave or per
+    // work-group), sized for the largest pass of any candidate
     double* flux_part = nullptr;
     int64_t flux_cap = 0;
     // batch
     bool batch = false;
     std::vector<BatchGrid> grids;
-    void* table_dev = nullptr;
-    void* table_host = nullptr;   // pinned
-    size_t table_cap = 0;         // bytes
-    hipEvent_t table_done = nullptr;
-    bool table_pending = false;
-    // constant-weight adjoint: the plan of the mirrored point list
+    void* table_dev = nullptr;            // one Stream2DGrid per grid
+    std::vector<unsigned char> table_shadow;  // what the device table holds (empty: unknown)
+    // constant-weight adjoint: the plan of the mirrored point list (host only)
     st_plan_s* mirror = nullptr;
     // ST_PLAN_GRAPH: the launches of the last run, captured and instantiated
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint64_t> graph_key;
-    std::vector<uint64_t> table_key;  // batch: arguments the device table was built for
 };
 
 namespace {
@@ -513,7 +511,7 @@ st_status fill_plan(st_plan_s* p, const st_pattern* pat, st_dtype storage, st_bo
     if (storage != ST_F64 && storage != ST_F32 && storage != ST_BF16)
         return fail(ST_ERR_ARG, "storage dtype %d unknown", static_cast<int>(storage));
     if (bc != ST_BC_ZERO && bc != ST_BC_PERIODIC) return fail(ST_ERR_ARG, "boundary %d unknown", static_cast<int>(bc));
-    if (flags & ~(ST_PLAN_AUTOTUNE | ST_PLAN_NAIVE | ST_PLAN_VARCOEF | ST_PLAN_GRAPH))
+    if (flags & ~(ST_PLAN_AUTOTUNE | ST_PLAN_NAIVE | ST_PLAN_VARCOEF | ST_PLAN_GRAPH | ST_PLAN_OWN_WORK))
         return fail(ST_ERR_ARG, "unknown flag bits 0x%x", flags);
     p->ndim = pat->ndim;
     p->dtype = storage;
@@ -749,20 +747,13 @@ int64_t flux_parts(const st_plan_s* p, const Candidate& c, bool fused, int tb) {
     return static_cast<int64_t>(g.tiles_x) * g.tiles_y * g.chunks_z * c.k3.nw;
 }
 
-st_status ensure_flux_parts(st_plan_s* p, int64_t need, hipStream_t s) {
-    if (need <= p->flux_cap) return ST_OK;
-    if (stream_capturing(s)) return fail(ST_ERR_CAPTURE, "the outflow partial sums need an allocation during capture");
-    if (p->flux_part) {
-        ST_HIP(hipStreamSynchronize(s), "hipStreamSynchronize before regrowing the outflow buffer");
-        hipFree(p->flux_part);
-        p->flux_part = nullptr;
-        p->flux_cap = 0;
-    }
-    if (hipMalloc(&p->flux_part, static_cast<size_t>(need) * sizeof(double)) != hipSuccess) {
-        p->flux_part = nullptr;
-        return fail(ST_ERR_NOMEM, "hipMalloc of %lld outflow partial sums failed", static_cast<long long>(need));
-    }
-    p->flux_cap = need;
+// The partial sums were sized when the plan was made (plan_buffers): a run
+// never allocates.
+st_status check_flux_parts(const st_plan_s* p, int64_t need) {
+    if (!p->flux_part) return fail(ST_ERR_HIP, "the plan holds no outflow buffer (made without a device?)");
+    if (need > p->flux_cap)
+        return fail(ST_ERR_UNSUPPORTED, "a pass needs %lld outflow partial sums, the plan holds %lld",
+                    static_cast<long long>(need), static_cast<long long>(p->flux_cap));
     return ST_OK;
 }
 
@@ -793,7 +784,7 @@ st_status run_steps(st_plan_s* p, const Candidate& c_in, void* grid, void* work,
             if (n < 0) return fail(ST_ERR_UNSUPPORTED, "tiling infeasible");
             need = std::max(need, n);
         }
-        if (st_status r = ensure_flux_parts(p, need, s); r != ST_OK) return r;
+        if (st_status r = check_flux_parts(p, need); r != ST_OK) return r;
         std::memset(&fb, 0, sizeof(fb));
         for (int d = 0; d < 3; ++d) fb.n[d] = p->n[d];
         fb.npoints = p->npoints;
@@ -989,7 +980,7 @@ st_status run_graphed(st_plan_s* p, const std::vector<uint64_t>& key, hipStream_
         ST_HIP(hipGraphLaunch(p->graph_exec, s), "hipGraphLaunch");
         return ST_OK;
     }
-    if (!p->cap_stream) ST_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    if (!p->cap_stream) return fail(ST_ERR_HIP, "the plan holds no capture stream (made without a device?)");
     if (p->graph_exec) {
         hipGraphExecDestroy(p->graph_exec);
         p->graph_exec = nullptr;
@@ -1046,16 +1037,8 @@ st_status prepare_run(st_plan_s* plan, void* grid, void*& work, const double* co
     for (int i = 0; i < plan->npoints; ++i)
         if (!std::isfinite(coeffs[i])) return fail(ST_ERR_ARG, "coefficient %d is not finite", i);
     if (st_status r = need_device(); r != ST_OK) return r;
-    const size_t bytes = static_cast<size_t>(plan_cells(plan)) * elem_bytes(plan->dtype);
     if (!work) {
-        if (!plan->owned_work) {
-            if (stream_capturing(s)) return fail(ST_ERR_CAPTURE, "work == NULL needs an allocation during capture");
-            if (hipMalloc(&plan->owned_work, bytes) != hipSuccess) {
-                plan->owned_work = nullptr;
-                return fail(ST_ERR_NOMEM, "hipMalloc(%zu) for the plan's work buffer failed", bytes);
-            }
-            plan->owned_bytes = bytes;
-        }
+        if (!plan->owned_work) return fail(ST_ERR_ARG, "work is NULL and the plan owns none (ST_PLAN_OWN_WORK)");
         work = plan->owned_work;
     }
     if (work == grid) return fail(ST_ERR_ARG, "work aliases grid");
@@ -1070,9 +1053,15 @@ const char* stencil_last_error(void) { return g_last_error.c_str(); }
 
 const char* stencil_version(void) { return "paper_2303_08365_amd stencil 0.1 (gfx950)"; }
 
-st_status stencil_plan(st_plan* out, const st_pattern* pattern, const int64_t* shape, st_dtype storage,
-                       st_boundary bc, uint32_t flags) {
-    if (!out) return fail(ST_ERR_ARG, "out is NULL");
+}  // extern "C"
+
+namespace {
+st_status plan_buffers(st_plan_s* p);
+
+// stencil_plan without the device buffers and the mirror (the mirror plan of
+// a constant-weight adjoint is made this way, host memory only).
+st_status make_plan(st_plan_s** out, const st_pattern* pattern, const int64_t* shape, st_dtype storage,
+                    st_boundary bc, uint32_t flags, bool full) {
     *out = nullptr;
     if (st_status r = check_pattern(pattern); r != ST_OK) return r;
     if (!shape) return fail(ST_ERR_ARG, "shape is NULL");
@@ -1089,14 +1078,41 @@ st_status stencil_plan(st_plan* out, const st_pattern* pattern, const int64_t* s
         p->n[3 - p->ndim + d] = shape[d];
     }
     build_candidates(p);
-    if (flags & ST_PLAN_AUTOTUNE) {
-        if (st_status r = autotune(p); r != ST_OK) {
-            delete p;
+    if (full) {
+        st_status r = plan_buffers(p);
+        if (r == ST_OK && (flags & ST_PLAN_AUTOTUNE)) r = autotune(p);
+        if (r == ST_OK && !(flags & ST_PLAN_VARCOEF)) {
+            // the adjoint of a constant-weight sweep is the sweep with every
+            // offset negated (same boundary): planned now, so the adjoint
+            // call allocates nothing
+            std::vector<int32_t> off(static_cast<size_t>(p->npoints) * p->ndim);
+            for (int i = 0; i < p->npoints; ++i) {
+                const int src = p->perm[i];  // caller's index of canonical point i
+                for (int d = 0; d < p->ndim; ++d)
+                    off[static_cast<size_t>(src) * p->ndim + d] = -p->off[i][3 - p->ndim + d];
+            }
+            const st_pattern mp{p->ndim, p->npoints, off.data()};
+            r = make_plan(&p->mirror, &mp, p->shape, storage, bc, flags & ST_PLAN_NAIVE, false);
+        }
+        if (r != ST_OK) {
+            stencil_plan_destroy(p);
             return r;
         }
     }
     *out = p;
     return ST_OK;
+}
+}  // namespace
+
+extern "C" {
+
+st_status stencil_plan(st_plan* out, const st_pattern* pattern, const int64_t* shape, st_dtype storage,
+                       st_boundary bc, uint32_t flags) {
+    if (!out) return fail(ST_ERR_ARG, "out is NULL");
+    st_plan_s* p = nullptr;
+    const st_status r = make_plan(&p, pattern, shape, storage, bc, flags, true);
+    *out = p;
+    return r;
 }
 
 st_status stencil_plan_destroy(st_plan plan) {
@@ -1104,8 +1120,6 @@ st_status stencil_plan_destroy(st_plan plan) {
     if (plan->owned_work) hipFree(plan->owned_work);
     if (plan->flux_part) hipFree(plan->flux_part);
     if (plan->table_dev) hipFree(plan->table_dev);
-    if (plan->table_host) hipHostFree(plan->table_host);
-    if (plan->table_done) hipEventDestroy(plan->table_done);
     if (plan->mirror) stencil_plan_destroy(plan->mirror);
     if (plan->graph_exec) hipGraphExecDestroy(plan->graph_exec);
     if (plan->cap_stream) hipStreamDestroy(plan->cap_stream);
@@ -1219,6 +1233,10 @@ extern "C" st_status stencil_batch_plan(st_plan* out, const st_pattern* pattern,
         delete p;
         return fail(ST_ERR_UNSUPPORTED, "batched plans take constant weights");
     }
+    if (flags & ST_PLAN_OWN_WORK) {
+        delete p;
+        return fail(ST_ERR_UNSUPPORTED, "batched plans take the caller's work buffers");
+    }
     if (p->radius != 1 || (p->cls != kStar && p->cls != kBox)) {
         delete p;
         return fail(ST_ERR_UNSUPPORTED, "batched plans take radius-1 star or box patterns");
@@ -1238,11 +1256,11 @@ extern "C" st_status stencil_batch_plan(st_plan* out, const st_pattern* pattern,
     build_candidates(p);
     // batch runs need a fused family; drop the naive fallback when one exists
     if (p->cands.size() > 1) p->cands.pop_back();
-    if (flags & ST_PLAN_AUTOTUNE) {
-        if (st_status r = batch_autotune(p); r != ST_OK) {
-            stencil_plan_destroy(p);
-            return r;
-        }
+    st_status r = plan_buffers(p);
+    if (r == ST_OK && (flags & ST_PLAN_AUTOTUNE)) r = batch_autotune(p);
+    if (r != ST_OK) {
+        stencil_plan_destroy(p);
+        return r;
     }
     *out = p;
     return ST_OK;
@@ -1286,121 +1304,121 @@ int64_t batch_chunk(const st_plan_s* p, const Candidate& c, int tb, const std::v
 
 namespace {
 
-struct BatchLaunch {
-    size_t first;   // first descriptor of this pass in the device table
-    int count;      // descriptors (grids still running)
-    int64_t items;  // work items of the pass
-};
+// Chunk length of a batch candidate: fixed for the plan (all grids, the
+// candidate's depth), so the device table's geometry never depends on the
+// run's arguments.
+int64_t batch_chunk_of(const st_plan_s* plan, const Candidate& c) {
+    if (c.chunk > 0) return c.chunk;
+    std::vector<int> all(plan->grids.size());
+    for (size_t g = 0; g < all.size(); ++g) all[g] = static_cast<int>(g);
+    return batch_chunk(plan, c, c.tb, all);
+}
 
-// Build the per-pass descriptor table for the call's arguments and upload it
-// (skipped when the arguments equal those of the previous upload).
-st_status batch_prepare(st_plan_s* plan, const Candidate& c, int32_t n, void* const* grids, void* const* works,
-                        const double* coeffs, const int64_t* steps, const std::vector<uint64_t>& key,
-                        hipStream_t s, std::vector<BatchLaunch>& launches, std::vector<int>& copies) {
-    std::vector<std::vector<int>> passes(n);
-    size_t npass = 0;
+// Work items of every grid of a batch candidate, summed (the launch size of
+// every pass; -1 when a grid cannot be tiled).
+int64_t batch_items(const st_plan_s* plan, const Candidate& c) {
+    const int64_t len = batch_chunk_of(plan, c);
+    if (len <= 0) return -1;
+    int64_t items = 0;
+    for (const BatchGrid& bg : plan->grids) {
+        Geo2 geo;
+        if (!geo2(c, bg.ny, bg.nx, c.tb, geo, len)) return -1;
+        items += geo.items;
+    }
+    return items;
+}
+
+// Build the per-grid descriptor table of a batch run.  Every pass is one
+// launch over all grids with the geometry of the candidate's depth; grid g
+// runs pass_list(steps[g]) -- `full` passes of that depth, then up to three
+// shorter tail passes (a tile with the full depth's halo computes any
+// smaller depth exactly) -- and its work-groups return at once in passes
+// beyond its own.  Odd passes read the work buffer and write the grid.
+st_status batch_table(st_plan_s* plan, const Candidate& c, int32_t n, void* const* grids, void* const* works,
+                      const double* coeffs, const int64_t* steps, std::vector<Stream2DGrid>& table, int& npass,
+                      int64_t& items, std::vector<int>& copies) {
+    const int64_t len = batch_chunk_of(plan, c);
+    if (len <= 0) return fail(ST_ERR_UNSUPPORTED, "2D tiling infeasible for the batch");
+    table.assign(static_cast<size_t>(n), Stream2DGrid{});
     copies.clear();
+    npass = 0;
+    items = 0;
     for (int g = 0; g < n; ++g) {
         bool copy = false;
-        passes[g] = pass_list(steps[g], c.tb, copy);
+        const std::vector<int> v = pass_list(steps[g], c.tb, copy);
         if (copy) copies.push_back(g);
-        npass = std::max(npass, passes[g].size());
+        int full = 0;
+        while (full < static_cast<int>(v.size()) && v[full] == c.tb) ++full;
+        if (static_cast<int>(v.size()) - full > 3)
+            return fail(ST_ERR_UNSUPPORTED, "pass schedule of grid %d has %zu tail passes", g, v.size() - full);
+        npass = std::max(npass, static_cast<int>(v.size()));
+        Geo2 geo;
+        if (!geo2(c, plan->grids[g].ny, plan->grids[g].nx, c.tb, geo, len))
+            return fail(ST_ERR_UNSUPPORTED, "2D tiling infeasible for grid %d", g);
+        Stream2DGrid& G = table[g];
+        std::memset(&G, 0, sizeof(G));
+        G.src = grids[g];
+        G.dst = works[g];
+        G.ny = plan->grids[g].ny;
+        G.nx = plan->grids[g].nx;
+        G.tiles_x = geo.tiles_x;
+        G.chunks_y = geo.chunks_y;
+        G.chunk_y = geo.chunk_y;
+        G.out_w = geo.out_w;
+        G.hxa = geo.hxa;
+        G.vec_ok = (G.nx % c.k2.vx == 0) && aligned16(grids[g]) && aligned16(works[g]);
+        G.tb = c.tb;
+        G.full = full;
+        for (int j = 0; j < 3; ++j) G.tail[j] = full + j < static_cast<int>(v.size()) ? v[full + j] : 0;
+        G.tile_begin = items;
+        G.items = geo.items;
+        G.gid = g;
+        canonical_weights(plan, coeffs + static_cast<int64_t>(g) * plan->npoints, G.w);
+        items += geo.items;
     }
-    std::vector<Stream2DGrid> table;
-    launches.clear();
-    std::vector<std::pair<int, int64_t>> chunk_for_tb;  // chunk length chosen per depth
-    for (size_t pi = 0; pi < npass; ++pi) {
-        const size_t first = table.size();
-        int64_t begin = 0;
-        for (int g = 0; g < n; ++g) {
-            if (pi >= passes[g].size()) continue;
-            const int tb = passes[g][pi];
-            int64_t len = 0;
-            for (const auto& ct : chunk_for_tb)
-                if (ct.first == tb) len = ct.second;
-            if (len == 0) {
-                std::vector<int> same;
-                for (int h = 0; h < n; ++h)
-                    if (pi < passes[h].size() && passes[h][pi] == tb) same.push_back(h);
-                len = c.chunk > 0 ? c.chunk : batch_chunk(plan, c, tb, same);
-                if (len <= 0) return fail(ST_ERR_UNSUPPORTED, "2D tiling infeasible for the batch");
-                chunk_for_tb.emplace_back(tb, len);
-            }
-            Geo2 geo;
-            if (!geo2(c, plan->grids[g].ny, plan->grids[g].nx, tb, geo, len))
-                return fail(ST_ERR_UNSUPPORTED, "2D tiling infeasible for grid %d", g);
-            Stream2DGrid G;
-            std::memset(&G, 0, sizeof(G));
-            const bool even = (pi % 2) == 0;
-            G.src = even ? grids[g] : works[g];
-            G.dst = even ? works[g] : grids[g];
-            G.ny = plan->grids[g].ny;
-            G.nx = plan->grids[g].nx;
-            G.tiles_x = geo.tiles_x;
-            G.chunks_y = geo.chunks_y;
-            G.chunk_y = geo.chunk_y;
-            G.out_w = geo.out_w;
-            G.hxa = geo.hxa;
-            G.vec_ok = (G.nx % c.k2.vx == 0) && aligned16(grids[g]) && aligned16(works[g]);
-            G.tb = tb;
-            G.tile_begin = begin;
-            G.items = geo.items;
-            G.gid = g;
-            canonical_weights(plan, coeffs + static_cast<int64_t>(g) * plan->npoints, G.w);
-            begin += geo.items;
-            table.push_back(G);
-        }
-        launches.push_back(BatchLaunch{first, static_cast<int>(table.size() - first), begin});
-    }
-    if (key == plan->table_key) return ST_OK;  // the device already holds this table
-    const size_t need = table.size() * sizeof(Stream2DGrid);
-    if (plan->table_pending) {
-        // the previous upload may still read the pinned buffer
-        ST_HIP(hipEventSynchronize(plan->table_done), "hipEventSynchronize(table)");
-        plan->table_pending = false;
-    }
-    if (need > plan->table_cap) {
-        if (stream_capturing(s)) return fail(ST_ERR_CAPTURE, "descriptor table growth during capture");
-        if (plan->table_dev) hipFree(plan->table_dev);
-        if (plan->table_host) hipHostFree(plan->table_host);
-        plan->table_dev = plan->table_host = nullptr;
-        plan->table_cap = 0;
-        if (hipMalloc(&plan->table_dev, need) != hipSuccess ||
-            hipHostMalloc(&plan->table_host, need, hipHostMallocDefault) != hipSuccess)
-            return fail(ST_ERR_NOMEM, "descriptor table allocation (%zu bytes) failed", need);
-        plan->table_cap = need;
-        if (!plan->table_done) ST_HIP(hipEventCreateWithFlags(&plan->table_done, hipEventDisableTiming), "hipEventCreate");
-    }
-    std::memcpy(plan->table_host, table.data(), need);
-    ST_HIP(hipMemcpyAsync(plan->table_dev, plan->table_host, need, hipMemcpyHostToDevice, s), "hipMemcpyAsync(table)");
-    ST_HIP(hipEventRecord(plan->table_done, s), "hipEventRecord(table)");
-    plan->table_pending = true;
-    plan->table_key = key;
     return ST_OK;
 }
 
-// With `flux` (one device double per grid), every pass runs the
-// outflow-summing twin and a per-grid reduction of its partial sums.
-st_status batch_launches(const st_plan_s* plan, const Candidate& c, const std::vector<BatchLaunch>& launches,
+// Put `table` into the plan's device table, in stream order (kernel-argument
+// upload: nothing is allocated and nothing waits).  Skipped when the device
+// already holds these bytes and nobody else can have rewritten them.
+st_status batch_upload(st_plan_s* plan, const std::vector<Stream2DGrid>& table, bool force, hipStream_t s) {
+    const size_t bytes = table.size() * sizeof(Stream2DGrid);
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(table.data());
+    if (!force && plan->table_shadow.size() == bytes && std::memcmp(plan->table_shadow.data(), b, bytes) == 0)
+        return ST_OK;
+    if (!plan->table_dev) return fail(ST_ERR_HIP, "the batch plan holds no device table (made without a device?)");
+    if (hipError_t e = launch_table_write(plan->table_dev, b, bytes, s); e != hipSuccess)
+        return hip_fail(e, "descriptor table upload");
+    plan->table_shadow.assign(b, b + bytes);
+    return ST_OK;
+}
+
+// The passes of a batch run.  With `flux` (one device double per grid),
+// every pass runs the outflow-summing twin and a per-grid reduction of its
+// partial sums.
+st_status batch_launches(const st_plan_s* plan, const Candidate& c, int npass, int64_t items,
                          const std::vector<int>& copies, void* const* grids, void* const* works, hipStream_t s,
                          double* flux = nullptr) {
     const Stream2DGrid* dev = static_cast<const Stream2DGrid*>(plan->table_dev);
+    const int n = static_cast<int>(plan->grids.size());
     Stream2DKey key = c.k2;
     if (flux) {
         key.flux = 1;
         if (!stream2d_has(key)) key.tbmax = 8;
     }
-    for (const BatchLaunch& L : launches) {
+    for (int pi = 0; pi < npass; ++pi) {
         Stream2DArgs a;
         std::memset(&a, 0, sizeof(a));
-        a.grids = dev + L.first;
-        a.ngrids = L.count;
-        a.items = L.items;
+        a.grids = dev;
+        a.ngrids = n;
+        a.pass = pi;
+        a.items = items;
         a.flux_part = flux ? plan->flux_part : nullptr;
         const hipError_t e = launch_stream2d(key, a, s);
         if (e != hipSuccess) return hip_fail(e, "stream2d batch launch");
         if (flux) {
-            const hipError_t r = launch_flux_reduce_batch(dev + L.first, L.count, plan->flux_part, flux, s);
+            const hipError_t r = launch_flux_reduce_batch(dev, n, plan->flux_part, flux, s);
             if (r != hipSuccess) return hip_fail(r, "outflow batch reduce launch");
         }
     }
@@ -1425,41 +1443,35 @@ st_status batch_run_impl(st_plan_s* plan, int32_t n, void* const* grids, void* c
         one.npoints = plan->npoints;
         std::memcpy(one.off, plan->off, sizeof(one.off));
         std::memcpy(one.perm, plan->perm, sizeof(one.perm));
-        for (int g = 0; g < n; ++g) {
+        // the outflow partial sums live in the batch plan's buffer
+        one.flux_part = plan->flux_part;
+        one.flux_cap = plan->flux_cap;
+        st_status r = ST_OK;
+        for (int g = 0; g < n && r == ST_OK; ++g) {
             if (steps[g] == 0) continue;
             one.n[1] = plan->grids[g].ny;
             one.n[2] = plan->grids[g].nx;
             double w[kMaxPoints];
             canonical_weights(plan, coeffs + static_cast<int64_t>(g) * plan->npoints, w);
-            // the outflow partial sums live in the batch plan's buffer
-            one.flux_part = plan->flux_part;
-            one.flux_cap = plan->flux_cap;
-            const st_status r = run_steps(&one, c, grids[g], works[g], w, steps[g], s, flux ? flux + g : nullptr);
-            plan->flux_part = one.flux_part;
-            plan->flux_cap = one.flux_cap;
-            one.flux_part = nullptr;
-            if (r != ST_OK) return r;
+            r = run_steps(&one, c, grids[g], works[g], w, steps[g], s, flux ? flux + g : nullptr);
         }
-        return ST_OK;
+        one.flux_part = nullptr;
+        return r;
     }
+    std::vector<Stream2DGrid> table;
+    int npass = 0;
+    int64_t items = 0;
+    std::vector<int> copies;
+    if (st_status r = batch_table(plan, c, n, grids, works, coeffs, steps, table, npass, items, copies); r != ST_OK)
+        return r;
     if (flux) {
         // eager launches (no graph): the passes with their per-grid reductions
-        std::vector<uint64_t> key;
-        key_push(key, static_cast<int64_t>(plan->sel));
-        for (int g = 0; g < n; ++g) {
-            key_push(key, grids[g]);
-            key_push(key, works[g]);
-            key_push(key, steps[g]);
-            for (int i = 0; i < plan->npoints; ++i) key_push(key, coeffs[static_cast<int64_t>(g) * plan->npoints + i]);
-        }
-        std::vector<BatchLaunch> launches;
-        std::vector<int> copies;
-        if (st_status r = batch_prepare(plan, c, n, grids, works, coeffs, steps, key, s, launches, copies); r != ST_OK)
-            return r;
-        int64_t need = 1;
-        for (const BatchLaunch& L : launches) need = std::max(need, L.items);
-        if (st_status r = ensure_flux_parts(plan, need, s); r != ST_OK) return r;
-        return batch_launches(plan, c, launches, copies, grids, works, s, flux);
+        if (st_status r = check_flux_parts(plan, items); r != ST_OK) return r;
+        const bool capturing = stream_capturing(s);
+        if (st_status r = batch_upload(plan, table, capturing, s); r != ST_OK) return r;
+        // a caller's graph may replay its own table later: forget ours
+        if (capturing) plan->table_shadow.clear();
+        return batch_launches(plan, c, npass, items, copies, grids, works, s, flux);
     }
     std::vector<uint64_t> key;
     key_push(key, static_cast<int64_t>(plan->sel));
@@ -1469,22 +1481,84 @@ st_status batch_run_impl(st_plan_s* plan, int32_t n, void* const* grids, void* c
         key_push(key, steps[g]);
         for (int i = 0; i < plan->npoints; ++i) key_push(key, coeffs[static_cast<int64_t>(g) * plan->npoints + i]);
     }
-    std::vector<BatchLaunch> launches;
-    std::vector<int> copies;
-    const bool replay = (plan->flags & ST_PLAN_GRAPH) && plan->graph_exec && key == plan->graph_key &&
-                        key == plan->table_key && !stream_capturing(s);
-    if (!replay) {
-        if (st_status r = batch_prepare(plan, c, n, grids, works, coeffs, steps, key, s, launches, copies); r != ST_OK)
-            return r;
+    if ((plan->flags & ST_PLAN_GRAPH) && !stream_capturing(s)) {
+        // the captured graph writes its own table before its passes, so
+        // every replay runs with the right descriptors
+        const st_status r = run_graphed(plan, key, s, [&](hipStream_t st) {
+            if (st_status u = batch_upload(plan, table, true, st); u != ST_OK) return u;
+            return batch_launches(plan, c, npass, items, copies, grids, works, st);
+        });
+        // captured now or replayed: the graph wrote this table (equal keys
+        // give equal tables)
+        if (r == ST_OK) {
+            const unsigned char* b = reinterpret_cast<const unsigned char*>(table.data());
+            plan->table_shadow.assign(b, b + table.size() * sizeof(Stream2DGrid));
+        } else {
+            plan->table_shadow.clear();
+        }
+        return r;
     }
-    return run_graphed(plan, key, s, [&](hipStream_t st) {
-        return batch_launches(plan, c, launches, copies, grids, works, st);
-    });
+    const bool capturing = stream_capturing(s);
+    if (st_status r = batch_upload(plan, table, capturing, s); r != ST_OK) return r;
+    if (capturing) plan->table_shadow.clear();
+    return batch_launches(plan, c, npass, items, copies, grids, works, s);
 }
 
 }  // namespace
 
 namespace {
+
+// Outflow partial sums a plan must hold: the most any pass of any candidate
+// writes (the fused twins write one per wave or work item, the band kernel
+// kFluxBandBlocks); none for periodic and variable-coefficient plans.
+int64_t flux_need(const st_plan_s* p) {
+    if (p->bc != kZero || (p->flags & ST_PLAN_VARCOEF)) return 0;
+    int64_t need = kFluxBandBlocks;
+    for (const Candidate& c : p->cands) {
+        if (p->batch) {
+            if (c.kernel == ST_KERNEL_STREAM2D) need = std::max(need, batch_items(p, c));
+            continue;
+        }
+        if (!flux_fused(p, c)) continue;
+        for (int t = 1; t <= c.tb; ++t) need = std::max(need, flux_parts(p, c, true, t));
+    }
+    return need;
+}
+
+// Every device buffer a plan owns, allocated once here so that no run call
+// allocates or waits: the work buffer (ST_PLAN_OWN_WORK), the outflow partial
+// sums, the batch descriptor table and the capture stream (ST_PLAN_GRAPH).
+// A plan made on a host without a device gets none of them: it can describe
+// its tilings but every run call reports the missing device.
+st_status plan_buffers(st_plan_s* p) {
+    if (!have_device()) return ST_OK;
+    if (p->flags & ST_PLAN_OWN_WORK) {
+        const size_t bytes = static_cast<size_t>(plan_cells(p)) * elem_bytes(p->dtype);
+        if (hipMalloc(&p->owned_work, bytes) != hipSuccess) {
+            p->owned_work = nullptr;
+            return fail(ST_ERR_NOMEM, "hipMalloc(%zu) for the plan's work buffer failed", bytes);
+        }
+    }
+    const int64_t need = flux_need(p);
+    if (need > 0) {
+        if (hipMalloc(&p->flux_part, static_cast<size_t>(need) * sizeof(double)) != hipSuccess) {
+            p->flux_part = nullptr;
+            return fail(ST_ERR_NOMEM, "hipMalloc of %lld outflow partial sums failed", static_cast<long long>(need));
+        }
+        p->flux_cap = need;
+    }
+    if (p->batch) {
+        const size_t bytes = p->grids.size() * sizeof(Stream2DGrid);
+        if (hipMalloc(&p->table_dev, bytes) != hipSuccess) {
+            p->table_dev = nullptr;
+            return fail(ST_ERR_NOMEM, "hipMalloc(%zu) for the batch descriptor table failed", bytes);
+        }
+    }
+    if (p->flags & ST_PLAN_GRAPH)
+        ST_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "hipStreamCreate(capture)");
+    return ST_OK;
+}
+
 st_status batch_entry(st_plan plan, int32_t n, void* const* grids, void* const* works, const double* coeffs,
                       const int64_t* steps, void* stream, double* flux) {
     if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
@@ -1553,7 +1627,7 @@ st_status batch_autotune(st_plan_s* p) {
         int best_i = p->sel;
         for (size_t i = 0; i < p->cands.size(); ++i) {
             p->sel = static_cast<int>(i);
-            p->table_key.clear();
+            p->table_shadow.clear();
             const int64_t st = std::max<int64_t>(2, 2 * p->cands[i].tb);
             std::vector<int64_t> steps(n, st);
             if (batch_run_impl(p, n, g.data(), w.data(), coeffs.data(), steps.data(), nullptr) != ST_OK) continue;
@@ -1572,7 +1646,7 @@ st_status batch_autotune(st_plan_s* p) {
         hipEventDestroy(e0);
         hipEventDestroy(e1);
         p->sel = best_i;
-        p->table_key.clear();
+        p->table_shadow.clear();
         p->flags = flags;
         tune_store(tkey, best_i, static_cast<int>(p->cands.size()));
         g_last_error.clear();
@@ -1704,21 +1778,7 @@ extern "C" st_status stencil_adjoint_run(st_plan plan, const void* k, double alp
         // same sweep with every offset negated
         if (k || grad_k) return fail(ST_ERR_MISMATCH, "k / grad_k given to a constant-weight plan");
         if (!coeffs) return fail(ST_ERR_ARG, "coeffs is NULL");
-        if (!plan->mirror) {
-            std::vector<int32_t> off(static_cast<size_t>(plan->npoints) * plan->ndim);
-            for (int i = 0; i < plan->npoints; ++i) {
-                const int src = plan->perm[i];  // caller's index of canonical point i
-                for (int d = 0; d < plan->ndim; ++d)
-                    off[static_cast<size_t>(src) * plan->ndim + d] = -plan->off[i][3 - plan->ndim + d];
-            }
-            st_pattern mp{plan->ndim, plan->npoints, off.data()};
-            st_plan m = nullptr;
-            if (st_status r = stencil_plan(&m, &mp, plan->shape, static_cast<st_dtype>(plan->dtype),
-                                           static_cast<st_boundary>(plan->bc), plan->flags & ST_PLAN_NAIVE);
-                r != ST_OK)
-                return r;
-            plan->mirror = m;
-        }
+        if (!plan->mirror) return fail(ST_ERR_MISMATCH, "the plan has no transposed sweep");
         return stencil_run(plan->mirror, lambda, work, coeffs, plan->shape, steps,
                            static_cast<st_boundary>(plan->bc), stream);
     }

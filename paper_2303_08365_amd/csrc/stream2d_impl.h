@@ -436,6 +436,8 @@ struct Kern {
         const int64_t item = __builtin_amdgcn_readfirstlane(static_cast<int>(wg * 4 + (threadIdx.x >> 6)));
         if (item >= a.items) return;
         const Stream2DGrid* gp = &a.one;
+        int tb;
+        bool odd = false;
         if (a.grids != nullptr) {
             int lo = 0, hi = a.ngrids - 1;
             while (lo < hi) {  // last grid whose tile_begin <= item
@@ -443,17 +445,31 @@ struct Kern {
                 if (a.grids[mid].tile_begin <= item) lo = mid; else hi = mid - 1;
             }
             gp = a.grids + lo;
+            // this grid's depth at pass a.pass: `full` passes of depth tb,
+            // then its tail passes; none left = nothing to do
+            const int32_t full = uni(gp->full);
+            const int32_t j = a.pass - full;
+            tb = j < 0 ? uni(gp->tb) : (j == 0 ? uni(gp->tail[0]) : (j == 1 ? uni(gp->tail[1]) : (j == 2 ? uni(gp->tail[2]) : 0)));
+            odd = (a.pass & 1) != 0;
+            if (tb <= 0) {
+                if constexpr (FLX) {
+                    if (lane == 0) a.flux_part[item] = 0.0;
+                }
+                return;
+            }
+        } else {
+            // the descriptor may live in global memory: pin every field to SGPRs
+            tb = uni(gp->tb);
         }
-        // the descriptor may live in global memory: pin every field to SGPRs
-        const int tb = uni(gp->tb);
         const int32_t tiles_x = uni(gp->tiles_x);
         const int32_t out_w = uni(gp->out_w);
         const int32_t hxa = uni(gp->hxa);
         const int32_t chunk_y = uni(gp->chunk_y);
         const bool vec_ok = uni(gp->vec_ok) != 0;
         Ctx c;
-        c.src = static_cast<const TS*>(uni(gp->src));
-        c.dst = static_cast<TS*>(uni(gp->dst));
+        // odd batch passes run from the work buffer back into the grid
+        c.src = static_cast<const TS*>(odd ? uni(gp->dst) : uni(gp->src));
+        c.dst = static_cast<TS*>(odd ? uni(const_cast<void*>(gp->src)) : uni(gp->dst));
         c.ny = static_cast<int32_t>(uni(gp->ny));
         c.nx = static_cast<int32_t>(uni(gp->nx));
         c.row_bytes = static_cast<uint32_t>(c.nx) * sizeof(TS);

@@ -276,3 +276,79 @@ def test_autotune_cache_file_validation(tmp_path):
     st.autotune_cache(None)
     with pytest.raises(st.StencilError):
         st.autotune_cache("")
+
+
+def test_binding_refuses_host_tensors_and_short_adjoint_buffers():
+    # every tensor the kernels touch must be GPU memory: a host pointer would
+    # reach a kernel; the adjoint's checkpoint list and segment buffer are
+    # sized before the call (the C side reads ceil(steps/every) pointers)
+    import torch
+    shp = (4, 8, 16)
+    cpu = torch.zeros(shp, dtype=torch.float64)
+    p = st.Plan(synth.star_offsets(3, 1), shp, "f64")
+    w = list(synth.heat_weights(3, 0.1))
+    with pytest.raises(ValueError, match="GPU tensor"):
+        p.run(cpu, w, 2)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        p.run_flux(cpu, w, 2, torch.zeros(1, dtype=torch.float64))
+    with pytest.raises(ValueError, match="GPU tensor"):
+        p.adjoint(cpu.clone(), 2, cpu.clone(), coeffs=w)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        st.copy(cpu.clone(), cpu)
+    vp = st.Plan(synth.star_offsets(3, 1), shp, "f64", varcoef=True)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        vp.run_ckpt(cpu.clone(), cpu.clone(), 0.1, 4, cpu.clone(), every=2, ckpts=[cpu.clone(), cpu.clone()])
+    with pytest.raises(ValueError, match="checkpoint tensors are required"):
+        vp.run_ckpt(cpu.clone(), cpu.clone(), 0.1, 4, cpu.clone(), every=2, ckpts=[cpu.clone()])
+    with pytest.raises(ValueError, match="checkpoint tensors are required"):
+        vp.adjoint(cpu.clone(), 10, cpu.clone(), k=cpu.clone(), alpha=0.1, ckpts=[cpu.clone()] * 2, every=4,
+                   seg=torch.zeros((3,) + shp, dtype=torch.float64))
+    with pytest.raises(ValueError, match="every must be >= 1"):
+        vp.adjoint(cpu.clone(), 10, cpu.clone(), k=cpu.clone(), alpha=0.1, ckpts=[cpu.clone()] * 3, every=0)
+    with pytest.raises(ValueError, match="seg must hold"):
+        vp.adjoint(cpu.clone(), 10, cpu.clone(), k=cpu.clone(), alpha=0.1, ckpts=[cpu.clone()] * 3, every=4)
+    with pytest.raises(ValueError, match="seg holds"):
+        vp.adjoint(cpu.clone(), 10, cpu.clone(), k=cpu.clone(), alpha=0.1, ckpts=[cpu.clone()] * 3, every=4,
+                   seg=torch.zeros((2,) + shp, dtype=torch.float64))
+    with pytest.raises(ValueError, match="plan's shape"):
+        vp.adjoint(cpu.clone(), 10, cpu.clone(), k=cpu.clone(), alpha=0.1,
+                   ckpts=[cpu.clone(), cpu.clone(), torch.zeros((4, 8, 8), dtype=torch.float64)], every=4,
+                   seg=torch.zeros((3,) + shp, dtype=torch.float64))
+    with pytest.raises(ValueError, match="GPU tensor"):
+        vp.adjoint(cpu.clone(), 10, cpu.clone(), k=cpu.clone(), alpha=0.1, ckpts=[cpu.clone()] * 3, every=4,
+                   seg=torch.zeros((3,) + shp, dtype=torch.float64))
+    bp = st.BatchPlan(synth.star_offsets(2, 1), [(8, 16), (9, 16)], "f32")
+    g = [torch.zeros(s, dtype=torch.float32) for s in [(8, 16), (9, 16)]]
+    with pytest.raises(ValueError, match="GPU tensor"):
+        bp.run(g, [x.clone() for x in g], [list(synth.heat_weights(2, 0.1, "f32"))] * 2, [2, 2])
+
+
+def _enclosing_functions(src, pattern):
+    """Names of the top-level functions of `src` whose bodies contain `pattern`
+    (a function starts at a column-0 line holding `name(` and ends at the
+    next column-0 `}`)."""
+    found = set()
+    current = None
+    for line in src.splitlines():
+        m = re.match(r"^[A-Za-z_][\w:<>,\s\*&]*?\b(\w+)\s*\(", line)
+        if m and not line.startswith(("#", "//", "namespace", "extern", "struct", "using", "template", "typedef")):
+            current = m.group(1)
+        if line.startswith("}"):
+            pass
+        if re.search(pattern, line) and not line.lstrip().startswith("//"):
+            found.add(current)
+    return found
+
+
+def test_run_calls_neither_allocate_nor_wait():
+    # every device allocation, free, stream creation and host wait of the
+    # library sits in plan creation, autotuning or plan destruction: no run
+    # entry point (stencil_run, _flux, _batch_run, _ckpt, _adjoint) reaches one
+    src = open(os.path.join(ROOT, "paper_2303_08365_amd", "csrc", "stencil_abi.cpp")).read()
+    allowed = {"plan_buffers", "autotune", "batch_autotune", "stencil_plan_destroy"}
+    for pat in (r"\bhipMalloc\w*\s*\(", r"\bhipHostMalloc\s*\(", r"\bhipFree\w*\s*\(", r"\bhipHostFree\s*\(",
+                r"Synchronize\s*\(", r"\bhipStreamCreate\w*\s*\(", r"\bhipEventCreate\w*\s*\(",
+                r"\bhipMallocAsync\s*\("):
+        where = _enclosing_functions(src, pat)
+        assert where <= allowed, (pat, where - allowed)
+    assert "ST_ERR_CAPTURE" not in src
