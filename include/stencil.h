@@ -257,7 +257,11 @@ st_status stencil_batch_plan(st_plan* out, const st_pattern* pattern, int32_t n,
  * the arguments differ from what it holds: the entries travel as kernel
  * arguments, so the call neither allocates nor waits, and a graph that
  * captures the call records the table it needs and rewrites it on every
- * replay.  Calls on one plan must not overlap on different streams.
+ * replay.  Once a call on a plan has been recorded into a caller's graph,
+ * every later call on that plan rewrites the table (a replay may have
+ * changed it at any time).  Calls on one plan must not overlap on different
+ * streams, and a caller's graph that holds a call on a plan must not replay
+ * concurrently with other calls on that plan.
  * Errors: ST_ERR_ARG, ST_ERR_MISMATCH (n differs from the plan), ST_ERR_HIP.
  */
 st_status stencil_batch_run(st_plan plan, int32_t n, void* const* grids, void* const* works,

@@ -189,6 +189,10 @@ struct st_plan_s {
     std::vector<BatchGrid> grids;
     void* table_dev = nullptr;            // one Stream2DGrid per grid
     std::vector<unsigned char> table_shadow;  // what the device table holds (empty: unknown)
+    // Set once a table upload has been recorded into a caller's graph: every
+    // replay of that graph rewrites the device table behind the library's
+    // back, so from then on the shadow is never trusted and every run uploads.
+    bool table_foreign = false;
     // constant-weight adjoint: the plan of the mirrored point list (host only)
     st_plan_s* mirror = nullptr;
     // ST_PLAN_GRAPH: the launches of the last run, captured and instantiated
@@ -1385,7 +1389,8 @@ st_status batch_table(st_plan_s* plan, const Candidate& c, int32_t n, void* cons
 st_status batch_upload(st_plan_s* plan, const std::vector<Stream2DGrid>& table, bool force, hipStream_t s) {
     const size_t bytes = table.size() * sizeof(Stream2DGrid);
     const unsigned char* b = reinterpret_cast<const unsigned char*>(table.data());
-    if (!force && plan->table_shadow.size() == bytes && std::memcmp(plan->table_shadow.data(), b, bytes) == 0)
+    if (!force && !plan->table_foreign && plan->table_shadow.size() == bytes &&
+        std::memcmp(plan->table_shadow.data(), b, bytes) == 0)
         return ST_OK;
     if (!plan->table_dev) return fail(ST_ERR_HIP, "the batch plan holds no device table (made without a device?)");
     if (hipError_t e = launch_table_write(plan->table_dev, b, bytes, s); e != hipSuccess)
@@ -1469,8 +1474,8 @@ st_status batch_run_impl(st_plan_s* plan, int32_t n, void* const* grids, void* c
         if (st_status r = check_flux_parts(plan, items); r != ST_OK) return r;
         const bool capturing = stream_capturing(s);
         if (st_status r = batch_upload(plan, table, capturing, s); r != ST_OK) return r;
-        // a caller's graph may replay its own table later: forget ours
-        if (capturing) plan->table_shadow.clear();
+        // a caller's graph may replay its own table at any later time
+        if (capturing) plan->table_foreign = true;
         return batch_launches(plan, c, npass, items, copies, grids, works, s, flux);
     }
     std::vector<uint64_t> key;
@@ -1500,7 +1505,7 @@ st_status batch_run_impl(st_plan_s* plan, int32_t n, void* const* grids, void* c
     }
     const bool capturing = stream_capturing(s);
     if (st_status r = batch_upload(plan, table, capturing, s); r != ST_OK) return r;
-    if (capturing) plan->table_shadow.clear();
+    if (capturing) plan->table_foreign = true;
     return batch_launches(plan, c, npass, items, copies, grids, works, s);
 }
 
