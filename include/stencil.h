@@ -197,6 +197,30 @@ st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs
                       const int64_t* shape, int64_t steps, st_boundary bc, void* stream);
 
 /*
+ * stencil_run_noalloc -- stencil_run for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It takes no work buffer: the passes ping-pong between
+ * `grid` and the library's static work space, a file-scope device array of
+ * 64 MiB (2^26 bytes) that each device the library runs on holds from the
+ * first call on that device until the process ends.  The call allocates
+ * nothing (no hipMalloc, no hipFree, no allocating library routine) and does
+ * not wait; its result equals stencil_run's bit for bit (same passes, same
+ * kernels).  ST_PLAN_GRAPH is ignored: the launches go to `stream`, or into
+ * the caller's capture.
+ *   plan, grid, coeffs, shape, steps, bc  as for stencil_run.
+ * Every call on one device shares that device's array and leaves it holding
+ * the last call's intermediate states; the array needs no clearing (every
+ * pass writes each cell it later reads).  Calls that overlap on one device
+ * -- on different streams, from different threads, or a replaying graph
+ * that holds such a call -- race on the array and give wrong results.
+ * Errors: as stencil_run; ST_ERR_ARG also when the grid needs more than the
+ * 64 MiB of work space (plan cells x storage bytes), checked before anything
+ * else touches the device.
+ */
+st_status stencil_run_noalloc(st_plan plan, void* grid, const double* coeffs, const int64_t* shape,
+                              int64_t steps, st_boundary bc, void* stream);
+
+/*
  * stencil_run_flux -- stencil_run that also keeps account of the heat the
  * steps carry out of the grid.  Reading the zero ghost layer of Alg. 1
  * (Sec. 2.1, Eq. 3) as an absorbing boundary, a step moves w_p * u(c) from

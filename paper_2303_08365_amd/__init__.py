@@ -101,6 +101,7 @@ def library():
             "stencil_plan_select": [P, i32, i32, i32],
             "stencil_run": [P, P, P, p_dbl, p_i64, i64, i32, P],
             "stencil_run_flux": [P, P, P, p_dbl, p_i64, i64, i32, P, P],
+            "stencil_run_noalloc": [P, P, p_dbl, p_i64, i64, i32, P],
             "stencil_batch_plan": [ctypes.POINTER(P), ctypes.POINTER(_Pattern), i32, p_i64, i32, i32, u32],
             "stencil_batch_run": [P, i32, ctypes.POINTER(P), ctypes.POINTER(P), p_dbl, p_i64, P],
             "stencil_batch_run_flux": [P, i32, ctypes.POINTER(P), ctypes.POINTER(P), p_dbl, p_i64, P, P],
@@ -244,6 +245,22 @@ class Plan:
         _check(library().stencil_run(self._h, grid.data_ptr(),
                                      work.data_ptr() if work is not None else None, w, shp,
                                      int(steps), self.bc, _stream_handle(stream)))
+        return grid
+
+    def run_noalloc(self, grid, coeffs, steps: int, stream=None):
+        """``stencil_run_noalloc``: `steps` steps in place on `grid` with the
+        library's static work space (no work tensor, nothing allocated)."""
+        if tuple(grid.shape) != self.shape:
+            raise ValueError(f"grid shape {tuple(grid.shape)} != plan shape {self.shape}")
+        if not grid.is_contiguous() or _tensor_dtype(grid) != self.dtype:
+            raise ValueError("grid must be a contiguous tensor of the plan's dtype")
+        _on_one_gpu((grid, "grid"))
+        w = _doubles(coeffs)
+        if len(w) != len(self.offsets):
+            raise ValueError("one coefficient per point")
+        shp = (ctypes.c_int64 * len(self.shape))(*self.shape)
+        _check(library().stencil_run_noalloc(self._h, grid.data_ptr(), w, shp, int(steps), self.bc,
+                                             _stream_handle(stream)))
         return grid
 
     def run_flux(self, grid, coeffs, steps: int, flux, work=None, stream=None):

@@ -185,4 +185,10 @@ hipError_t launch_copy(void* dst, const void* src, int64_t bytes, int cus, hipSt
 // may be reused at once and nothing waits; dst 4-byte aligned, bytes % 4 == 0
 hipError_t launch_table_write(void* dst, const void* src, size_t bytes, hipStream_t s);
 
+// Static work space (noalloc.hip): a file-scope device array of
+// kStaticWorkBytes, its address on the current device looked up once per
+// device.  Used only by stencil_run_noalloc.
+constexpr size_t kStaticWorkBytes = size_t(64) << 20;
+hipError_t static_work(void** ptr, size_t* bytes);
+
 }  // namespace st

@@ -1019,7 +1019,8 @@ namespace {
 // Checks shared by stencil_run and stencil_run_flux; picks the work buffer
 // and rounds the weights.  `nothing` is set when there are no steps.
 st_status prepare_run(st_plan_s* plan, void* grid, void*& work, const double* coeffs, const int64_t* shape,
-                      int64_t steps, st_boundary bc, hipStream_t s, double* wcan, bool& nothing) {
+                      int64_t steps, st_boundary bc, hipStream_t s, double* wcan, bool& nothing,
+                      bool static_work_space = false) {
     nothing = false;
     if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
     if (plan->batch) return fail(ST_ERR_MISMATCH, "batch plan passed to stencil_run");
@@ -1041,6 +1042,10 @@ st_status prepare_run(st_plan_s* plan, void* grid, void*& work, const double* co
     for (int i = 0; i < plan->npoints; ++i)
         if (!std::isfinite(coeffs[i])) return fail(ST_ERR_ARG, "coefficient %d is not finite", i);
     if (st_status r = need_device(); r != ST_OK) return r;
+    if (static_work_space) {
+        size_t cap = 0;
+        if (hipError_t e = static_work(&work, &cap); e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    }
     if (!work) {
         if (!plan->owned_work) return fail(ST_ERR_ARG, "work is NULL and the plan owns none (ST_PLAN_OWN_WORK)");
         work = plan->owned_work;
@@ -1183,6 +1188,25 @@ st_status stencil_run(st_plan plan, void* grid, void* work, const double* coeffs
     }
     const Candidate cand = plan->cands[plan->sel];
     return run_graphed(plan, key, s, [&](hipStream_t st) { return run_steps(plan, cand, grid, work, wcan, steps, st); });
+}
+
+st_status stencil_run_noalloc(st_plan plan, void* grid, const double* coeffs, const int64_t* shape, int64_t steps,
+                              st_boundary bc, void* stream) {
+    if (!plan) return fail(ST_ERR_ARG, "plan is NULL");
+    const size_t bytes = static_cast<size_t>(plan_cells(plan)) * elem_bytes(plan->dtype);
+    if (!plan->batch && bytes > kStaticWorkBytes)
+        return fail(ST_ERR_ARG, "the grid holds %zu bytes; the static work space of stencil_run_noalloc holds %zu",
+                    bytes, kStaticWorkBytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double wcan[kMaxPoints];
+    bool nothing = false;
+    void* work = nullptr;
+    if (st_status r = prepare_run(plan, grid, work, coeffs, shape, steps, bc, s, wcan, nothing, true);
+        r != ST_OK || nothing)
+        return r;
+    // eager launches whatever the plan's flags (no graph is instantiated
+    // here); inside a caller's capture they are recorded into its graph
+    return run_steps(plan, plan->cands[plan->sel], grid, work, wcan, steps, s);
 }
 
 st_status stencil_run_flux(st_plan plan, void* grid, void* work, const double* coeffs, const int64_t* shape,

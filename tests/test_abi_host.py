@@ -145,6 +145,56 @@ def test_run_rejects_bad_arguments_before_launch():
     assert lib.stencil_plan_destroy(None) == 0
 
 
+def test_run_noalloc_validation_and_work_space_limit():
+    # the allocation-free run takes no work buffer; a grid beyond its 64 MiB
+    # static work space is refused before anything touches the device
+    lib = st.library()
+    P = ctypes.c_void_p
+    w7 = (ctypes.c_double * 7)(*synth.heat_weights(3, 0.1))
+    big = (512, 512, 512)                       # FP64: 1 GiB
+    rc, h, keep = _raw_plan(synth.star_offsets(3, 1), big)
+    assert rc == 0
+    shp = (ctypes.c_int64 * 3)(*big)
+    assert lib.stencil_run_noalloc(h, P(FAKE), w7, shp, 3, 0, None) == -1
+    assert b"static work space" in lib.stencil_last_error()
+    lib.stencil_plan_destroy(h)
+    # exactly 64 MiB passes the size check (256^3 FP32), one cell more fails
+    for shape, dtype, ok in [((256, 256, 256), 1, True), ((256, 256, 257), 1, False),
+                             ((512, 512, 128), 2, True), ((1, 1, 8 * 2 ** 20 + 1), 0, False)]:
+        rc, h, keep = _raw_plan(synth.star_offsets(3, 1), shape, dtype=dtype)
+        assert rc == 0
+        s3 = (ctypes.c_int64 * 3)(*shape)
+        # steps = 0 is a no-op once the size is accepted
+        assert (lib.stencil_run_noalloc(h, P(FAKE), w7, s3, 0, 0, None) == 0) == ok, shape
+        lib.stencil_plan_destroy(h)
+    rc, h, keep = _raw_plan(synth.star_offsets(2, 1), (40, 50))
+    w5 = (ctypes.c_double * 5)(*synth.heat_weights(2, 0.1))
+    good = (ctypes.c_int64 * 2)(40, 50)
+    bad = (ctypes.c_int64 * 2)(40, 51)
+    assert lib.stencil_run_noalloc(None, P(FAKE), w5, good, 3, 0, None) == -1     # no plan
+    assert lib.stencil_run_noalloc(h, P(FAKE), w5, bad, 3, 0, None) == -3         # shape
+    assert lib.stencil_run_noalloc(h, P(FAKE), w5, good, 3, 1, None) == -3        # boundary
+    assert lib.stencil_run_noalloc(h, P(FAKE), w5, good, -1, 0, None) == -1       # steps < 0
+    assert lib.stencil_run_noalloc(h, None, w5, good, 3, 0, None) == -1           # no grid
+    assert lib.stencil_run_noalloc(h, P(FAKE), None, good, 3, 0, None) == -1      # no coeffs
+    assert lib.stencil_run_noalloc(h, P(FAKE), w5, good, 0, 0, None) == 0         # no-op
+    lib.stencil_plan_destroy(h)
+    bp = st.BatchPlan(synth.star_offsets(2, 1), [(8, 16)], "f32")
+    assert lib.stencil_run_noalloc(bp._h, P(FAKE), w5, good, 3, 0, None) == -3    # batch plan
+
+
+def test_static_work_space_is_a_file_scope_device_array_looked_up_per_device():
+    # the array is never named in host code except through the symbol lookup
+    src = open(os.path.join(ROOT, "paper_2303_08365_amd", "csrc", "noalloc.hip")).read()
+    assert re.search(r"static __device__ __align__\(256\) unsigned char scratch\[kStaticWorkBytes\]", src)
+    uses = [l for l in src.splitlines() if re.search(r"\bscratch\b", l) and not l.lstrip().startswith("//")]
+    assert len(uses) == 2 and "HIP_SYMBOL(scratch)" in uses[1], uses
+    abi = open(os.path.join(ROOT, "paper_2303_08365_amd", "csrc", "stencil_abi.cpp")).read()
+    body = abi[abi.index("st_status stencil_run_noalloc("):]
+    body = body[:body.index("\n}\n")]
+    assert not re.search(r"hipMalloc|hipFree|run_graphed|hipGraph|Synchronize", body)
+
+
 def test_batch_plan_and_run_validation():
     lib = st.library()
     shapes = [(37, 300), (256, 1000), (1024, 77)]
@@ -291,6 +341,8 @@ def test_binding_refuses_host_tensors_and_short_adjoint_buffers():
         p.run(cpu, w, 2)
     with pytest.raises(ValueError, match="GPU tensor"):
         p.run_flux(cpu, w, 2, torch.zeros(1, dtype=torch.float64))
+    with pytest.raises(ValueError, match="GPU tensor"):
+        p.run_noalloc(cpu, w, 2)
     with pytest.raises(ValueError, match="GPU tensor"):
         p.adjoint(cpu.clone(), 2, cpu.clone(), coeffs=w)
     with pytest.raises(ValueError, match="GPU tensor"):
