@@ -4,6 +4,9 @@ launch.  No kernel runs here."""
 import ctypes
 import os
 import re
+import struct
+import subprocess
+import tempfile
 
 import pytest
 
@@ -404,3 +407,57 @@ def test_run_calls_neither_allocate_nor_wait():
         where = _enclosing_functions(src, pat)
         assert where <= allowed, (pat, where - allowed)
     assert "ST_ERR_CAPTURE" not in src
+
+
+def _gpu_code_objects(so_path):
+    """The gfx950 code objects bundled into the library's .hip_fatbin section
+    (one clang offload bundle per translation unit)."""
+    readelf = "/opt/rocm/llvm/bin/llvm-readelf"
+    out = subprocess.run([readelf, "-S", "-W", so_path], capture_output=True, text=True, check=True).stdout
+    off = size = None
+    for line in out.splitlines():
+        if ".hip_fatbin" in line:
+            f = line.split("]", 1)[1].split()
+            off, size = int(f[3], 16), int(f[4], 16)
+    assert off is not None, "no .hip_fatbin section"
+    with open(so_path, "rb") as fh:
+        fh.seek(off)
+        data = fh.read(size)
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    objs, pos = [], 0
+    while True:
+        i = data.find(magic, pos)
+        if i < 0:
+            return objs
+        n = struct.unpack_from("<Q", data, i + len(magic))[0]
+        p = i + len(magic) + 8
+        for _ in range(n):
+            o, s, ts = struct.unpack_from("<QQQ", data, p)
+            p += 24
+            triple = data[p:p + ts].decode()
+            p += ts
+            if "amdgcn" in triple and s > 0:
+                objs.append(data[i + o:i + o + s])
+        pos = i + len(magic)
+
+
+def test_kernels_contain_no_device_function_calls():
+    # Every kernel is inlined into one function that ends in s_endpgm: no
+    # device-function call, hence no return address.  An earlier build
+    # outlined the bfloat16 radius-2 2D body into a call; the compiler's
+    # long-branch expansion in that function reused the return-address pair
+    # s[30:31], and waves leaving early through that branch (work items past
+    # the item count) then "returned" into their own branch target forever.
+    objdump = "/opt/rocm/llvm/bin/llvm-objdump"
+    if not os.path.exists(objdump):
+        pytest.skip("llvm-objdump is not installed")
+    objs = _gpu_code_objects(st.library_path())
+    assert len(objs) >= 10
+    with tempfile.TemporaryDirectory() as d:
+        for k, b in enumerate(objs):
+            f = os.path.join(d, f"co{k}.o")
+            with open(f, "wb") as fh:
+                fh.write(b)
+            dis = subprocess.run([objdump, "-d", f], capture_output=True, text=True, check=True).stdout
+            assert "s_swappc_b64" not in dis, f"code object {k} contains a device-function call"
+            assert "s_setpc_b64 s[30:31]" not in dis, f"code object {k} jumps through the return-address pair"

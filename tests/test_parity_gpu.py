@@ -29,9 +29,6 @@ def _weights(offsets, seed=0, dtype="f64"):
 def test_2d_all_candidates_match_oracle(dtype, bc, pattern, shape):
     import paper_2303_08365_amd as st
     r = 2 if pattern.endswith("_r2") else 1
-    if r == 2 and dtype == "bf16":
-        pytest.skip("bfloat16 radius-2 2D streaming kernels are switched off: a run of the box/periodic case "
-                    "stopped responding and its cause is not established (the plan uses the one-step kernel)")
     offs = synth.star_offsets(2, r) if pattern.startswith("star") else synth.box_offsets(2, r)
     w = _weights(offs, 1, dtype)
     steps = 4 if dtype == "bf16" else 11
