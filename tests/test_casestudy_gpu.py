@@ -48,8 +48,11 @@ def test_case_study_scaled_fp64_matches_closed_form_and_fp32_tracks_it():
     err64 = oracle.rel_l2(u64, ref)
     print(f"centre: closed form {ref[c, c]:.6f} FP64 {u64[c, c]:.6f} FP32 {u32[c, c]:.6f}; "
           f"FP64 rel-L2 {err64:.3e}", flush=True)
-    # 59375 FP64 steps: rounding of about 1e-16 per step and cell
-    assert err64 <= 1e-10
+    # 59375 FP64 steps: rounding of about 1e-16 per step and cell, averaging
+    # out over the steps (about sqrt(59375) x 1e-16 = 2.4e-14 per cell in a
+    # random walk; measured 2.5e-12: the rounding of a smooth field is
+    # correlated from step to step); bar 1e-11
+    assert err64 <= 1e-11
     # total + outflow: FP64 to rounding, FP32 to its states' drift
     s0 = float(u0.sum())
     d64 = (u64.sum() + out64 - s0) / s0

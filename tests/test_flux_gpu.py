@@ -3,6 +3,8 @@ oracle's FP64 outflow, on the same seeded inputs; the grid must end
 bit-identical to stencil_run's; fused (in-pass) and one-step (band kernel)
 sums must agree; at the full 512^3 heat size, total + outflow must stay
 equal to the initial total."""
+import math
+
 import numpy as np
 import pytest
 
@@ -29,10 +31,10 @@ def _ref_flux(u0, offs, w, steps, dtype):
 def _flux_tol(offs, w, shape, steps, dtype, u0):
     if dtype != "bf16":
         return TOL[dtype]
-    # each state differs from the exact one by at most t * 2^-9 * max|u0|; the
+    # each state differs from the exact one by at most t * 2^-8 * max|u0|; the
     # step's outflow weighs the band with the leaving weights (sum W_leave)
     _, wleave = oracle.sweep_flux(np.ones(shape), offs, np.abs(np.asarray(w)), 1)
-    return wleave * steps * steps * 2.0 ** -9 * float(np.max(np.abs(u0)))
+    return wleave * steps * steps * 2.0 ** -8 * float(np.max(np.abs(u0)))
 
 
 def _close(got, ref, tol, dtype, what):
@@ -84,10 +86,20 @@ def test_fused_and_one_step_outflow_agree(dtype, shape):
     plan.select(kernel=0)
     g2, f2 = _run_flux(plan, u0, w, 10, dtype)
     assert np.array_equal(g1, g2)
-    # FP64: the same products, summed in another order.  FP32 compute: the
-    # fused 3D kernels first add up to K = 4 rows of an x-face column in FP32
-    # (relative error at most 3 * 2^-24 of that part, all values >= 0 here)
-    tol = 1e-13 if dtype == "f64" else 3 * 2.0 ** -24
+    # FP64: the same products, summed in another order.  FP32 compute (3D):
+    # the fused kernels first add up to K = 4 rows of an x-face column in
+    # FP32, each such sum off by at most 3 * 2^-24 of itself (values >= 0);
+    # the outflow adds N of them over the states of the run, with rounding
+    # errors of either sign, so the total's relative error is of order
+    # 3 * 2^-24 / sqrt(N): the bar is ten times that.  2D kernels add face
+    # cells in FP64 directly.
+    if dtype == "f64" or nd == 2:
+        tol = 1e-13
+    else:
+        nz, ny, nx = shape
+        n_sums = 2 * nz * ((ny + 3) // 4) * 10  # two x faces, K = 4 rows per sum, 10 states
+        tol = 10 * 3 * 2.0 ** -24 / math.sqrt(n_sums)
+    print(f"fused vs band outflow: relative gap {abs(f1 - f2) / abs(f2):.2e}, bar {tol:.2e}", flush=True)
     assert abs(f1 - f2) <= tol * abs(f2), (f1, f2)
 
 

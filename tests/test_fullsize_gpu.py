@@ -1,9 +1,11 @@
 """Parity at the full workload sizes, in the launch configurations bench.py
-times (each plan's default candidate).  The oracle cannot sweep these grids
-in seconds, so the checks are: cells sampled one by one on their dependency
-cone (oracle_sweep_point), closed forms that hold at any size (sin-mode decay
-under the zero rule, FFT / DST-I spectral solutions), conservation, and
-directional finite differences for the gradients."""
+times (each plan's default candidate).  The headline 512^3 runs are compared
+with the oracle cell by cell over the whole grid (its OpenMP loops sweep
+512^3 x 100 steps in about 15 s on the host's cores); the batch with the DST-I
+solution of every grid; the others with cells sampled one by one on their
+dependency cone (oracle_sweep_point), closed forms that hold at any size
+(sin-mode decay under the zero rule, FFT spectral solutions), conservation,
+and directional finite differences for the gradients."""
 import math
 
 import numpy as np
@@ -12,7 +14,7 @@ import scipy.fft
 
 import oracle
 import synth
-from gpu_helpers import to_device, to_host
+from gpu_helpers import TOL, to_device, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -26,40 +28,44 @@ def _run(u0, offs, w, steps, bc, dtype):
     return g, plan
 
 
-def test_heat3d_512_fp64_mode_decay_and_sampled_cells():
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_heat3d_512_whole_grid_matches_oracle(dtype):
+    # the headline workload as bench.py runs it (default plan, 100 steps),
+    # every cell against the oracle on the same (rounded) inputs and weights
+    n, T, alpha = 512, 100, 0.15
+    offs = synth.star_offsets(3, 1)
+    wdt = "f64" if dtype == "f64" else "f32"
+    w = synth.heat_weights(3, alpha, wdt)
+    u0 = synth.round_to(synth.uniform_field((n, n, n), seed=0) + synth.sin_mode((n, n, n)), dtype)
+    g, plan = _run(u0, offs, w, T, "zero", dtype)
+    print("plan", plan.info(), flush=True)
+    got = to_host(g)
+    del g
+    ref = oracle.sweep(u0, offs, synth.round_to(np.asarray(w), wdt), T, bc="zero")
+    err = oracle.rel_l2(got, ref)
+    worst = float(np.max(np.abs(got - ref)))
+    print(f"heat3d 512^3 {dtype}: rel-L2 {err:.3e}, max |delta| {worst:.3e}", flush=True)
+    assert err <= TOL[dtype]
+    # per cell: the bar times the largest value (values lie in [0, 2))
+    assert worst <= TOL[dtype] * float(np.max(np.abs(ref)))
+
+
+def test_heat3d_512_fp64_mode_decay():
+    # linearity isolates the mode: run(noise + mode) - run(noise) = g^T mode
     n, T, alpha = 512, 100, 0.15
     offs = synth.star_offsets(3, 1)
     w = synth.heat_weights(3, alpha)
     noise = synth.uniform_field((n, n, n), seed=0)
     mode = synth.sin_mode((n, n, n))
-    u0 = noise + mode
-    g, plan = _run(u0, offs, w, T, "zero", "f64")
-    print("plan", plan.info(), flush=True)
+    g, _ = _run(noise + mode, offs, w, T, "zero", "f64")
     got = to_host(g)
     del g
-    # cells sampled on their dependency cone (corner, faces, interior)
-    for p in [(0, 0, 0), (511, 511, 511), (0, 255, 511), (256, 0, 300), (137, 402, 3)]:
-        ref = oracle.sweep_point(u0, offs, w, T, p, bc="zero")
-        assert abs(got[p] - ref) <= 1e-12 * max(1.0, abs(ref)), p
-    # linearity isolates the mode: run(noise + mode) - run(noise) = g^T mode
     gn, _ = _run(noise, offs, w, T, "zero", "f64")
     diff = got - to_host(gn)
     del gn
     gfac = 1.0 - 4.0 * alpha * 3 * math.sin(math.pi / (2.0 * (n + 1))) ** 2
     assert abs(gfac ** T - 0.998313783162922) < 1e-15
     assert np.max(np.abs(diff - gfac ** T * mode)) <= 1e-12
-
-
-def test_heat3d_512_fp32_sampled_cells():
-    n, T = 512, 100
-    offs = synth.star_offsets(3, 1)
-    w = synth.heat_weights(3, 0.15, "f32")
-    u0 = synth.round_to(synth.uniform_field((n, n, n), seed=0) + synth.sin_mode((n, n, n)), "f32")
-    g, _ = _run(u0, offs, w, T, "zero", "f32")
-    got = to_host(g)
-    for p in [(0, 0, 0), (300, 511, 17), (255, 256, 257)]:
-        ref = oracle.sweep_point(u0, offs, w, T, p, bc="zero")
-        assert abs(got[p] - ref) <= 1e-5 * abs(ref), p
 
 
 def _fft_star_symbol(shape, offs, w):
@@ -145,10 +151,8 @@ def test_batch64_500_steps_matches_dst_solutions(dtype):
     grids = [to_device(u, dtype) for u in u0s]
     works = [torch.empty_like(x) for x in grids]
     bp.run(grids, works, coeffs, [500] * 64)
-    sizes = [a * b for a, b in shapes]
-    check = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 33, 50})
     tol = 1e-12 if dtype == "f64" else 1e-5
-    for gi in check:
+    for gi in range(64):
         ref = _dst_star2d(u0s[gi], float(coeffs[gi][0]), float(coeffs[gi][1]), 500)
         err = oracle.rel_l2(to_host(grids[gi]), ref)
         print(f"batch {dtype} grid {gi} {shapes[gi]} rel-L2 {err:.2e}", flush=True)
@@ -176,7 +180,10 @@ def test_varcoef_256_gradients_match_directional_fd_and_fp64():
     _, gu32, gk32 = out["f32"]
     e_u, e_k = oracle.rel_l2(gu32, gu64), oracle.rel_l2(gk32, gk64)
     print(f"256^3 FP32 vs FP64 gradients: dL/du0 {e_u:.2e}, dL/dk {e_k:.2e}", flush=True)
-    assert e_u <= 1e-4 and e_k <= 1e-3
+    # dL/du0 keeps the FP32 bar; every dL/dk term is a product of two first
+    # differences of smooth fields, whose relative error exceeds the
+    # operands' by the fields' roughness ratio (10 here): one decade looser
+    assert e_u <= 1e-5 and e_k <= 1e-4
     # directional central difference of the FP64 loss along seeded directions
     rng = np.random.default_rng(11)
     vu = rng.standard_normal((n, n, n))
