@@ -103,6 +103,9 @@ typedef struct {
     int64_t lds_bytes;        /* LDS per work-group                             */
     int32_t variant;          /* index of the tiling candidate                  */
     int32_t ncandidates;      /* tiling candidates valid for this plan          */
+    int32_t pipeline;         /* ST_KERNEL_STREAM3D: 0 = queued planes, else    */
+                              /* the partial-sum pipeline (LDS buffers * 10 +   */
+                              /* prefetched planes)                            */
 } st_plan_info;
 
 /*

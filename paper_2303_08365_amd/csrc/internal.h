@@ -90,6 +90,8 @@ struct Stream3DKey {
     int32_t late;  // one-plane prefetch issued after step 0 (fewer registers)
     int32_t ylds;  // step-0 y neighbours through LDS too, the tile's halo rows loaded once
     int32_t flux;  // also sums the outflow of every step of the pass (zero rule)
+    int32_t pipe;  // 0: queued planes (stream3d_impl.h); NB*10+PD: radius-1 partial-sum
+                   // pipeline with NB LDS buffers and PD prefetched planes (pipe3d_impl.h)
 };
 hipError_t launch_stream3d(const Stream3DKey& k, const Stream3DArgs& a, hipStream_t s);
 bool stream3d_has(const Stream3DKey& k);

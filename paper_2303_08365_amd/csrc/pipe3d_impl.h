@@ -1,0 +1,385 @@
+// pipe3d_impl.h -- 3D radius-1 stars (7 points) with T_b steps fused per
+// pass: the z pipeline kept as partial sums, one LDS exchange per plane.
+//
+// Same tiling as the 2.5-D kernel of stream3d_impl.h (paper Sec. 4.1: an xy
+// tile held on chip while the work-group streams along z; Sec. 4.2: tiles
+// staged on chip so global accesses stay coalesced): lane L of wave w holds
+// columns X0 + L*VX .. +VX-1 of rows Y0 + w*K .. +K-1, x neighbours come
+// from the lane's own registers or lane +-1 through DPP, y neighbours from
+// the wave's own rows or, for its first and last row, from the neighbouring
+// waves through LDS.  What differs is how the z direction is kept.
+//
+// The canonical order of a 7-point star evaluates the point at z+1 last:
+//   u'(z) = fma(w6, u(z+1), P(z)),
+//   P(z)  = w0 u(z) -> z-1 -> y-1 -> x-1 -> x+1 -> y+1  (one mul, five fma).
+// Level l (the state after l fused steps) therefore keeps only two planes
+// per lane: its previous plane u_l(z-1) and the partial sum P_l(z-1) of the
+// next level.  When plane u_l(z) arrives, fma(w6, u_l(z), P_l(z-1)) is
+// already the finished plane u_{l+1}(z-1) -- it needs no neighbour exchange
+// -- so one iteration first runs that completion through all levels (phase
+// A: level 0's new input plane yields level 1's plane, which yields level
+// 2's, ...; the last level's is stored), then exchanges the edge rows of
+// every level's new plane through LDS behind ONE barrier (phase B), then
+// starts every level's next partial sum (phase C).  Against three queued
+// planes per level and a barrier per level this needs two thirds of the
+// registers and a quarter of the barriers (four fused steps), with the same
+// arithmetic bit for bit.
+//
+// Level l is exact on the register tile shrunk by l columns per side in x
+// (the DPP shifts bring 0 into lanes 0 and 63) and, in y, by l-1 rows per
+// side (level 0's rows just outside the tile are loaded once per tile and
+// pass through LDS like the wave edge rows, later levels see 0 there).  The
+// planner's tiles keep hxa >= tb columns and hya >= tb-1 rows of halo.  Under
+// the zero rule a tile that would cross the grid edge is moved inward to
+// touch it, where those zeros are the ghost layer, so edge tiles are exact up
+// to the edge.  A plane outside the grid is a ghost plane: level 0 loads it
+// as 0 (empty descriptor range); a deeper level's value there is never used,
+// because the z weights that would read it are set to 0 for that iteration
+// (scalar selects, nothing per element; exact for finite states).
+//
+// Memory access: one buffer descriptor per plane (range = the plane, empty
+// for a ghost plane) and, per row, one 32-bit vector offset fixed for the
+// whole pass (the row and the lane's columns), so a load or store of a whole
+// row is one instruction with no per-row descriptor.  Rows that are not
+// output rows, lanes whose columns lie outside the output tile, and halo rows
+// outside the grid use an offset past the range's end: the hardware drops
+// such a store and returns 0 for such a load.  (The range check covers the
+// vector offset only, so the scalar offset stays 0.)  Needs planes below
+// 2 GiB, whole-vector rows, and under the zero rule nx >= 64*VX, ny >= NW*K.
+#pragma once
+
+#include <utility>
+
+#include "dev_common.h"
+#include "registry.h"
+
+namespace st {
+
+namespace p3d {
+
+template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD>
+struct Pipe {
+    using S = Storage<TS>;
+    using TC = typename S::TC;
+    static_assert(NW >= 2 && K >= 2, "a tile needs two waves of two rows");
+    static_assert(NB == 1 || NB == 2, "one or two LDS buffers");
+    static_assert(PD >= 1 && PD <= 2, "one or two planes prefetched");
+    static constexpr int W = 64 * VX;
+    static constexpr int H = NW * K;
+    // LDS rows of one level: slot 0 the tile's halo row above, 2w+1 and 2w+2
+    // the first and last row of wave w, 2*NW+1 the halo row below, 2*NW+2 a
+    // sink for waves that own no halo row.  Wave w reads its row above from
+    // slot 2w and its row below from slot 2w+3.
+    static constexpr int SLOTS = 2 * NW + 3;
+    static constexpr int LEVEL_ELEMS = SLOTS * W;
+    static constexpr int BUF_ELEMS = TBMAX * LEVEL_ELEMS;
+    static constexpr int LDS_BYTES = NB * BUF_ELEMS * static_cast<int>(sizeof(TC));
+    static constexpr uint32_t kOut = 0x80000000u;  // past the end of any plane (planes < 2 GiB)
+    static constexpr int32_t kRsrcWord3 = 0x00020000;  // gfx9: raw 32-bit data
+    static constexpr int kNT = 2;                      // stores: non-temporal
+
+    struct Ctx {
+        const TS* src;
+        TS* dst;
+        int32_t nz;
+        uint32_t plane_bytes, row_bytes;
+        int32_t zs, ze, zlast;
+        uint32_t lo[K];        // byte offset of this lane's columns in each of the wave's rows
+        uint32_t so[K];        // same for the stores; kOut outside the output tile
+        uint32_t ho;           // same for this wave's halo row; kOut: none, or a ghost row
+        int hslot;             // the halo row's LDS slot
+        int lane, wave;
+        TC w[7];
+    };
+
+    static __device__ __forceinline__ bool zghost(int32_t z, int32_t nz) {
+        return !PER && static_cast<uint32_t>(z) >= static_cast<uint32_t>(nz);
+    }
+    static __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_in(const Ctx& c, int32_t zin) {
+        const int32_t zz = PER ? wrap_idx(zin < c.zlast ? zin : c.zlast, c.nz) : (zin < c.zlast ? zin : c.zlast);
+        const bool out = zghost(zz, c.nz);
+        const TS* base = out ? c.src : c.src + static_cast<int64_t>(zz) * (c.plane_bytes / sizeof(TS));
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<TS*>(base), 0, out ? 0 : c.plane_bytes, kRsrcWord3);
+    }
+    static __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_out(const Ctx& c, int32_t z) {
+        const bool ok = static_cast<uint32_t>(z - c.zs) < static_cast<uint32_t>(c.ze - c.zs);
+        TS* base = ok ? c.dst + static_cast<int64_t>(z) * (c.plane_bytes / sizeof(TS)) : c.dst;
+        return __builtin_amdgcn_make_buffer_rsrc(base, 0, ok ? c.plane_bytes : 0, kRsrcWord3);
+    }
+
+    static __device__ __forceinline__ void ldrow(__amdgpu_buffer_rsrc_t r, uint32_t vo, TC (&v)[VX]) {
+        constexpr int kBytes = VX * static_cast<int>(sizeof(TS));
+        static_assert(kBytes == 8 || kBytes % 16 == 0, "rows are read in 8- or 16-byte pieces");
+        TS vals[VX];
+        if constexpr (kBytes % 16 == 0) {
+            u32x4 raw[kBytes / 16];
+#pragma unroll
+            for (int i = 0; i < kBytes / 16; ++i)
+                raw[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, vo + 16 * i, 0, 0));
+            __builtin_memcpy(vals, raw, kBytes);
+        } else {
+            const u32x2 raw = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(r, vo, 0, 0));
+            __builtin_memcpy(vals, &raw, kBytes);
+        }
+#pragma unroll
+        for (int e = 0; e < VX; ++e) v[e] = S::widen(vals[e]);
+    }
+    static __device__ __forceinline__ void strow(__amdgpu_buffer_rsrc_t r, uint32_t vo, const TC (&v)[VX]) {
+        constexpr int kBytes = VX * static_cast<int>(sizeof(TS));
+        TS vals[VX];
+#pragma unroll
+        for (int e = 0; e < VX; ++e) vals[e] = S::narrow(v[e]);
+        if constexpr (kBytes % 16 == 0) {
+            u32x4 raw[kBytes / 16];
+            __builtin_memcpy(raw, vals, kBytes);
+#pragma unroll
+            for (int i = 0; i < kBytes / 16; ++i) __builtin_amdgcn_raw_buffer_store_b128(raw[i], r, vo + 16 * i, 0, kNT);
+        } else {
+            u32x2 raw;
+            __builtin_memcpy(&raw, vals, kBytes);
+            __builtin_amdgcn_raw_buffer_store_b64(raw, r, vo, 0, kNT);
+        }
+    }
+
+    // The wave's K rows of input plane zin and its halo row (if it owns one).
+    static __device__ __forceinline__ void load_plane(const Ctx& c, int32_t zin, TC (&v)[K][VX], TC (&h)[VX]) {
+        const __amdgpu_buffer_rsrc_t r = plane_in(c, zin);
+#pragma unroll
+        for (int k = 0; k < K; ++k) ldrow(r, c.lo[k], v[k]);
+        ldrow(r, c.ho, h);
+    }
+
+    template <int TB>
+    struct State {
+        TC prev[TB][K][VX];   // u_l(z-1)
+        TC pend[TB][K][VX];   // P_l(z-1): u_{l+1}(z-1) short of its z+1 term
+        TC pf[PD][K][VX];     // prefetched input planes
+        TC hpf[PD][VX];       // their halo rows
+    };
+
+    // One iteration: input plane zin enters level 0.
+    template <int TB, int J>
+    static __device__ __forceinline__ void step(const Ctx& c, int32_t it, int32_t zfirst, State<TB>& s, TC* lds) {
+        const int32_t zin = zfirst + it;
+        TC cur[TB][K][VX];
+        TC halo[VX];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int e = 0; e < VX; ++e) cur[0][k][e] = s.pf[J][k][e];
+#pragma unroll
+        for (int e = 0; e < VX; ++e) halo[e] = s.hpf[J][e];
+        load_plane(c, zin + PD, s.pf[J], s.hpf[J]);
+
+        // phase A: u_{l+1}(zin-l-1) = fma(w6, u_l(zin-l), P_l(zin-l-1)); a ghost
+        // plane zin-l (levels >= 1 hold junk there) enters with weight 0
+#pragma unroll
+        for (int l = 0; l < TB; ++l) {
+            const TC w6 = (l > 0 && zghost(zin - l, c.nz)) ? TC(0) : c.w[6];
+            if (l + 1 < TB) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) cur[l + 1][k][e] = S::round(fma_c(w6, cur[l][k][e], s.pend[l][k][e]));
+            } else {
+                const __amdgpu_buffer_rsrc_t r = plane_out(c, zin - TB);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    TC o[VX];
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) o[e] = fma_c(w6, cur[l][k][e], s.pend[l][k][e]);
+                    strow(r, c.so[k], o);
+                }
+            }
+        }
+
+        // phase B: edge rows of every level's new plane (and level 0's halo
+        // row) through LDS, one barrier
+        TC* buf = lds + (NB == 2 ? (it & 1) * BUF_ELEMS : 0);
+#pragma unroll
+        for (int l = 0; l < TB; ++l) {
+            TC* lv = buf + l * LEVEL_ELEMS + c.lane * VX;
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                lv[(2 * c.wave + 1) * W + e] = cur[l][0][e];
+                lv[(2 * c.wave + 2) * W + e] = cur[l][K - 1][e];
+            }
+        }
+        {
+            TC* lv = buf + c.hslot * W + c.lane * VX;
+#pragma unroll
+            for (int e = 0; e < VX; ++e) lv[e] = halo[e];
+        }
+        __syncthreads();
+
+        // phase C: the next partial sums
+#pragma unroll
+        for (int l = 0; l < TB; ++l) {
+            const TC* lv = buf + l * LEVEL_ELEMS + c.lane * VX;
+            TC above[VX], below[VX];
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                above[e] = lv[(2 * c.wave) * W + e];
+                below[e] = lv[(2 * c.wave + 3) * W + e];
+            }
+            const TC w1 = (l > 0 && zghost(zin - l - 1, c.nz)) ? TC(0) : c.w[1];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const TC lft = from_lower_z(cur[l][k][VX - 1]);
+                const TC rgt = from_upper_z(cur[l][k][0]);
+#pragma unroll
+                for (int e = 0; e < VX; ++e) {
+                    TC acc = c.w[0] * cur[l][k][e];
+                    acc = fma_c(w1, s.prev[l][k][e], acc);
+                    acc = fma_c(c.w[2], k > 0 ? cur[l][k > 0 ? k - 1 : 0][e] : above[e], acc);
+                    acc = fma_c(c.w[3], e > 0 ? cur[l][k][e > 0 ? e - 1 : 0] : lft, acc);
+                    acc = fma_c(c.w[4], e + 1 < VX ? cur[l][k][e + 1 < VX ? e + 1 : 0] : rgt, acc);
+                    acc = fma_c(c.w[5], k + 1 < K ? cur[l][k + 1 < K ? k + 1 : 0][e] : below[e], acc);
+                    s.pend[l][k][e] = acc;
+                    s.prev[l][k][e] = cur[l][k][e];
+                }
+            }
+        }
+        if constexpr (NB == 1) __syncthreads();  // the next iteration rewrites the buffer
+    }
+
+    template <int TB, int... J>
+    static __device__ __forceinline__ void group(const Ctx& c, int32_t base, int32_t zfirst, State<TB>& s, TC* lds,
+                                                 std::integer_sequence<int, J...>) {
+        (step<TB, J>(c, base + J, zfirst, s, lds), ...);
+    }
+    template <int TB, int... J>
+    static __device__ __forceinline__ void tail(const Ctx& c, int32_t base, int32_t nit, int32_t zfirst, State<TB>& s,
+                                                TC* lds, std::integer_sequence<int, J...>) {
+        ((base + J < nit ? step<TB, J>(c, base + J, zfirst, s, lds) : void()), ...);
+    }
+
+    template <int TB>
+    static __device__ __forceinline__ void run_tb(Ctx& c, TC* lds) {
+        const int32_t zfirst = c.zs - TB;
+        const int32_t nit = (c.ze - c.zs) + 2 * TB;
+        c.zlast = zfirst + nit - 1;
+        // halo slots of the levels >= 1 hold 0 for the whole pass
+        for (int i = threadIdx.x; i < NB * TBMAX * W; i += blockDim.x) {
+            const int b = i / (TBMAX * W), l = (i / W) % TBMAX, col = i % W;
+            if (l == 0) continue;
+            TC* lv = lds + b * BUF_ELEMS + l * LEVEL_ELEMS;
+            lv[col] = TC(0);
+            lv[(2 * NW + 1) * W + col] = TC(0);
+        }
+        __syncthreads();
+        State<TB> s;
+#pragma unroll
+        for (int l = 0; l < TB; ++l)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int e = 0; e < VX; ++e) {
+                    s.prev[l][k][e] = TC(0);
+                    s.pend[l][k][e] = TC(0);
+                }
+#pragma unroll
+        for (int p = 0; p < PD; ++p) load_plane(c, zfirst + p, s.pf[p], s.hpf[p]);
+        int32_t base = 0;
+        for (; base + PD <= nit; base += PD) group<TB>(c, base, zfirst, s, lds, std::make_integer_sequence<int, PD>{});
+        tail<TB>(c, base, nit, zfirst, s, lds, std::make_integer_sequence<int, PD>{});
+    }
+
+    static __device__ __forceinline__ void run(const Stream3DArgs& a, TC* lds) {
+        Ctx c;
+        c.lane = threadIdx.x & 63;
+        c.wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+        const uint32_t tiles = static_cast<uint32_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
+        const uint32_t item = static_cast<uint32_t>(xcd_remap(blockIdx.x, gridDim.x));
+        if (item >= tiles) return;
+        const uint32_t txy = item / static_cast<uint32_t>(a.tiles_x);
+        const int32_t tx = static_cast<int32_t>(item - txy * a.tiles_x);
+        const int32_t ty = static_cast<int32_t>(txy % static_cast<uint32_t>(a.tiles_y));
+        const int32_t cz = static_cast<int32_t>(txy / static_cast<uint32_t>(a.tiles_y));
+        const int32_t nx = static_cast<int32_t>(a.nx), ny = static_cast<int32_t>(a.ny);
+        c.src = static_cast<const TS*>(a.src);
+        c.dst = static_cast<TS*>(a.dst);
+        c.nz = static_cast<int32_t>(a.nz);
+        c.row_bytes = static_cast<uint32_t>(nx) * sizeof(TS);
+        c.plane_bytes = static_cast<uint32_t>(ny) * c.row_bytes;
+        const int32_t ox0 = tx * a.out_w, oy0 = ty * a.out_h;
+        const int32_t ox1 = ox0 + a.out_w < nx ? ox0 + a.out_w : nx;
+        const int32_t oy1 = oy0 + a.out_h < ny ? oy0 + a.out_h : ny;
+        int32_t X0 = ox0 - a.hxa, Y0 = oy0 - a.hya;
+        if (!PER) {  // move edge tiles inward (exact: the ghost layer is 0)
+            X0 = X0 < 0 ? 0 : (X0 + W > nx ? nx - W : X0);
+            Y0 = Y0 < 0 ? 0 : (Y0 + H > ny ? ny - H : Y0);
+        }
+        const int32_t xl = X0 + c.lane * VX;
+        const int32_t yw = Y0 + c.wave * K;
+        const int32_t x0 = PER ? wrap_idx(xl, nx) : xl;
+        const bool xown = xl >= ox0 && xl < ox1;  // whole lanes: out_w, hxa and nx are multiples of VX
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            // zero rule: rows yw + k lie in the grid (the tile was moved inward)
+            const int32_t yk = PER ? wrap_idx(yw + k, ny) : yw + k;
+            const uint32_t off = static_cast<uint32_t>(yk * nx + x0) * sizeof(TS);
+            c.lo[k] = off;
+            c.so[k] = (xown && yw + k >= oy0 && yw + k < oy1) ? off : kOut;
+        }
+        {
+            // halo rows: wave 0 the row above the tile, wave NW-1 the row below
+            const bool top = c.wave == 0, bot = c.wave == NW - 1;
+            const int32_t hy = top ? Y0 - 1 : Y0 + H;
+            const bool valid = (top || bot) && (PER || static_cast<uint32_t>(hy) < static_cast<uint32_t>(ny));
+            const int32_t hyw = PER ? wrap_idx(hy, ny) : hy;
+            c.ho = valid ? static_cast<uint32_t>(hyw * nx + x0) * sizeof(TS) : kOut;
+            c.hslot = top ? 0 : (bot ? 2 * NW + 1 : 2 * NW + 2);
+        }
+        c.zs = cz * a.chunk_z;
+        c.ze = c.zs + a.chunk_z < c.nz ? c.zs + a.chunk_z : c.nz;
+#pragma unroll
+        for (int p = 0; p < 7; ++p) c.w[p] = static_cast<TC>(a.w[p]);
+        const int tb = a.tb;
+        if constexpr (TBMAX >= 4) if (tb == 4) return run_tb<4>(c, lds);
+        if constexpr (TBMAX >= 3) if (tb == 3) return run_tb<3>(c, lds);
+        if constexpr (TBMAX >= 2) if (tb == 2) return run_tb<2>(c, lds);
+        run_tb<1>(c, lds);
+    }
+};
+
+template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD>
+__global__ __launch_bounds__(64 * NW) void pipe3d_kernel(const Stream3DArgs a) {
+    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    P::run(a, reinterpret_cast<typename P::TC*>(smem));
+}
+
+template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD>
+void launch(const Stream3DArgs& a, hipStream_t s) {
+    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD>;
+    const int64_t tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
+    hipLaunchKernelGGL((pipe3d_kernel<TS, TBMAX, VX, K, NW, PER, NB, PD>), dim3(static_cast<unsigned>(tiles)),
+                       dim3(64 * NW), P::LDS_BYTES, s, a);
+}
+
+template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD>
+int occ_of() {
+    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD>;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pipe3d_kernel<TS, TBMAX, VX, K, NW, PER, NB, PD>, 64 * NW,
+                                                     P::LDS_BYTES) != hipSuccess)
+        n = 0;
+    return n;
+}
+
+template <typename TS> constexpr int32_t dtype_of();
+template <> constexpr int32_t dtype_of<double>() { return kF64; }
+template <> constexpr int32_t dtype_of<float>() { return kF32; }
+template <> constexpr int32_t dtype_of<bf16s>() { return kBF16; }
+
+// Key: radius 1, whole-vector rows, pipe = NB * 10 + PD (no late / ylds / flux).
+#define P3D_ENTRY(TS, TBM, VX, K, NW, PER, NB, PD)                                                          \
+    Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, 1, TBM, VX, K, NW, 1, 0, 0, 0, (NB) * 10 + (PD)}, \
+           &launch<TS, TBM, VX, K, NW, PER, NB, PD>, Pipe<TS, TBM, VX, K, NW, PER, NB, PD>::LDS_BYTES,               \
+           &occ_of<TS, TBM, VX, K, NW, PER, NB, PD>}
+#define P3D_BC(TS, TBM, VX, K, NW, NB, PD) \
+    P3D_ENTRY(TS, TBM, VX, K, NW, false, NB, PD), P3D_ENTRY(TS, TBM, VX, K, NW, true, NB, PD)
+
+}  // namespace p3d
+}  // namespace st

@@ -35,5 +35,6 @@ Table3 s3d_table_r1_f64();
 Table3 s3d_table_r1_f32();
 Table3 s3d_table_r1_bf16();
 Table3 s3d_table_r4();
+Table3 p3d_table_r1();
 
 }  // namespace st

@@ -16,13 +16,14 @@ const Entry2* find2(const Stream2DKey& k) {
     return nullptr;
 }
 const Entry3* find3(const Stream3DKey& k) {
-    const Table3 tabs[] = {s3d_table_r1_f64(), s3d_table_r1_f32(), s3d_table_r1_bf16(), s3d_table_r4()};
+    const Table3 tabs[] = {s3d_table_r1_f64(), s3d_table_r1_f32(), s3d_table_r1_bf16(), s3d_table_r4(),
+                           p3d_table_r1()};
     for (const Table3& t : tabs)
         for (int i = 0; i < t.n; ++i) {
             const Stream3DKey& e = t.e[i].key;
             if (e.dtype == k.dtype && e.bc == k.bc && e.radius == k.radius && e.tbmax == k.tbmax &&
                 e.vx == k.vx && e.k == k.k && e.nw == k.nw && e.fast == k.fast && e.late == k.late &&
-                e.ylds == k.ylds && e.flux == k.flux)
+                e.ylds == k.ylds && e.flux == k.flux && e.pipe == k.pipe)
                 return &t.e[i];
         }
     return nullptr;

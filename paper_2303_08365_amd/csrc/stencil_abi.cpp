@@ -314,7 +314,11 @@ bool geo3(const Candidate& c, const int64_t n[3], int tb, Geo3& g) {
     // 32-bit integers: planes below 2 GiB, every extent below 2^30
     if (n[1] * n[2] * elem_bytes(c.k3.dtype) >= (int64_t(1) << 31)) return false;
     if (n[0] >= (int64_t(1) << 30) || n[1] >= (int64_t(1) << 30) || n[2] >= (int64_t(1) << 30)) return false;
-    g.hxa = static_cast<int32_t>(round_up(static_cast<int64_t>(R) * (tb - 1), vx));
+    // the queued-plane kernel brings the R columns beyond its register tile
+    // to step 0 (x ring); the partial-sum pipeline does not, so its level l
+    // is exact l*R columns in from each side
+    const int64_t hx = c.k3.pipe ? static_cast<int64_t>(R) * tb : static_cast<int64_t>(R) * (tb - 1);
+    g.hxa = static_cast<int32_t>(round_up(hx, vx));
     g.hya = R * (tb - 1);
     g.out_w = 64 * vx - 2 * g.hxa;
     g.out_h = H - 2 * g.hya;
@@ -389,18 +393,23 @@ void build_candidates(st_plan_s* p) {
     }
     if (!force_naive && p->ndim == 3 && p->cls == kStar && (p->radius == 1 || p->radius == 4)) {
         // ylds: step-0 y neighbours through LDS, the tile's halo rows loaded once
-        struct V { int vx, k, nw, late, ylds; };
+        struct V { int vx, k, nw, late, ylds, pipe; };
         std::vector<V> vs;
         if (p->radius == 1) {
             // first: the fastest measured on MI355X for 512^3 at the default depth
+            // the partial-sum pipeline (pipe = NB*10 + PD) first: with two
+            // LDS buffers it measured 1032 / 1572 Gcell/s (FP64 / FP32, four
+            // fused steps) against 740 / 1394 for the queued-plane kernel
             if (p->dtype == kF64)
-                vs = {{2, 4, 8, 1, 1}, {2, 4, 8, 1, 0}, {2, 4, 8, 0, 0}, {2, 4, 4, 0, 0}, {2, 2, 8, 0, 0},
-                      {2, 3, 8, 1, 0}, {2, 4, 8, 0, 1}, {2, 5, 8, 1, 1}};
+                vs = {{2, 4, 8, 0, 0, 21}, {2, 4, 8, 1, 1}, {2, 4, 8, 1, 0}, {2, 4, 8, 0, 0}, {2, 4, 4, 0, 0},
+                      {2, 2, 8, 0, 0}, {2, 3, 8, 1, 0}, {2, 4, 8, 0, 1}, {2, 5, 8, 1, 1},
+                      {2, 4, 8, 0, 0, 11}, {2, 3, 8, 0, 0, 21}};
             else if (p->dtype == kF32)
-                vs = {{4, 4, 8, 1, 1}, {4, 4, 8, 1, 0}, {4, 4, 8, 0, 0}, {4, 4, 4, 0, 0}, {4, 2, 8, 0, 0},
-                      {4, 3, 8, 1, 0}, {4, 4, 8, 0, 1}, {4, 5, 8, 1, 1}};
+                vs = {{4, 4, 8, 0, 0, 21}, {4, 4, 8, 1, 1}, {4, 4, 8, 1, 0}, {4, 4, 8, 0, 0}, {4, 4, 4, 0, 0},
+                      {4, 2, 8, 0, 0}, {4, 3, 8, 1, 0}, {4, 4, 8, 0, 1}, {4, 5, 8, 1, 1},
+                      {4, 4, 8, 0, 0, 11}, {4, 3, 8, 0, 0, 21}};
             else
-                vs = {{4, 4, 8, 0, 1}, {4, 4, 4, 0, 0}};
+                vs = {{4, 4, 8, 0, 1}, {4, 4, 4, 0, 0}, {4, 4, 8, 0, 0, 21}, {8, 4, 8, 0, 0, 11}};
         } else {
             // radius 4: the y halo through LDS (ylds) loads 2R rows per tile
             // instead of 2R per wave
@@ -418,10 +427,14 @@ void build_candidates(st_plan_s* p) {
                         c.kernel = ST_KERNEL_STREAM3D;
                         c.tb = tb;
                         c.chunk = ch;
-                        c.k3 = Stream3DKey{p->dtype, p->bc, p->radius, tbmax, v.vx, v.k, v.nw, 1, v.late, v.ylds};
-                        if (stream3d_has(c.k3) && have_device()) c.occ = stream3d_occupancy(c.k3);
+                        c.k3 = Stream3DKey{p->dtype, p->bc, p->radius, tbmax, v.vx, v.k, v.nw, 1, v.late, v.ylds,
+                                           0, v.pipe};
+                        if (!stream3d_has(c.k3)) continue;
+                        // on a device, only tilings whose LDS it can give
+                        if (have_device() && stream3d_lds_bytes(c.k3) > device_lds_limit()) continue;
+                        if (have_device()) c.occ = stream3d_occupancy(c.k3);
                         Geo3 g;
-                        if (stream3d_has(c.k3) && geo3(c, p->n, tb, g)) {
+                        if (geo3(c, p->n, tb, g)) {
                             fast.push_back(c);
                             break;
                         }
@@ -429,10 +442,10 @@ void build_candidates(st_plan_s* p) {
                 }
             }
         }
-        // measured on MI355X (512^3, radius 1, 20 steps): four fused steps with
-        // the step-0 halo through LDS and late prefetch for FP64 and FP32 (773
-        // and 1408 Gcell/s; three: 725 and 1290); bfloat16 storage halves the
-        // bytes, so one step already runs near the HBM rate (1380 Gcell/s)
+        // measured on MI355X (512^3, radius 1, 24 steps): four fused steps of
+        // the pipeline for FP64 and FP32 (1032 and 1572 Gcell/s; three: 916
+        // and 1497); bfloat16 storage halves the bytes, so one step already
+        // runs near the HBM rate (1380 Gcell/s)
         const int want = (p->radius == 1 && p->dtype != kBF16) ? 4 : 1;
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
             return (a.tb == want && a.chunk == 0) > (b.tb == want && b.chunk == 0);
@@ -684,6 +697,15 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
         key.fast = vec_ok && (p->bc == kPeriodic ||
                               (p->n[2] >= 64 * key.vx && p->n[1] >= static_cast<int64_t>(key.k) * key.nw));
         key.flux = fpart ? 1 : 0;
+        if (key.pipe && (!key.fast || fpart)) {
+            // the pipeline has whole-vector rows only and no outflow sums: this
+            // pass runs on a queued-plane tiling of the plan (same result bit
+            // for bit)
+            for (const Candidate& o : p->cands)
+                if (o.kernel == ST_KERNEL_STREAM3D && !o.k3.pipe && o.k3.tbmax >= tb)
+                    return launch_pass(p, o, src, dst, wcan, tb, vec_ok, s, fpart);
+            return fail(ST_ERR_UNSUPPORTED, "no queued-plane 3D tiling for a pass of depth %d", tb);
+        }
         const int lds = stream3d_lds_bytes(key);
         if (lds > device_lds_limit())
             return fail(ST_ERR_UNSUPPORTED, "tiling needs %d bytes of LDS, the device allows %d", lds,
@@ -867,6 +889,7 @@ void describe(const st_plan_s* p, const Candidate& c, int index, st_plan_info* i
         info->block = 64 * c.k3.nw;
         info->workgroups = static_cast<int64_t>(g.tiles_x) * g.tiles_y * g.chunks_z;
         info->lds_bytes = stream3d_lds_bytes(c.k3);
+        info->pipeline = c.k3.pipe;
     }
 }
 
