@@ -280,6 +280,18 @@ struct Pipe {
                 }
 #pragma unroll
         for (int p = 0; p < PD; ++p) load_plane(c, zfirst + p, s.pf[p], s.hpf[p]);
+        {
+            // stores into an empty range (the hardware drops them): the loop
+            // is then entered, as it is repeated, with the plane loads followed
+            // by one plane's stores in flight, so the wait for the loads at the
+            // top of the loop need not wait for the stores
+            const __amdgpu_buffer_rsrc_t none = plane_out(c, c.ze);
+            TC zero[VX];
+#pragma unroll
+            for (int e = 0; e < VX; ++e) zero[e] = TC(0);
+#pragma unroll
+            for (int k = 0; k < K; ++k) strow(none, c.so[k], zero);
+        }
         int32_t base = 0;
         for (; base + PD <= nit; base += PD) group<TB>(c, base, zfirst, s, lds, std::make_integer_sequence<int, PD>{});
         tail<TB>(c, base, nit, zfirst, s, lds, std::make_integer_sequence<int, PD>{});

@@ -409,7 +409,7 @@ void build_candidates(st_plan_s* p) {
                       {4, 2, 8, 0, 0}, {4, 3, 8, 1, 0}, {4, 4, 8, 0, 1}, {4, 5, 8, 1, 1},
                       {4, 4, 8, 0, 0, 11}, {4, 3, 8, 0, 0, 21}};
             else
-                vs = {{4, 4, 8, 0, 1}, {4, 4, 4, 0, 0}, {4, 4, 8, 0, 0, 21}, {8, 4, 8, 0, 0, 11}};
+                vs = {{4, 4, 8, 0, 0, 21}, {4, 4, 8, 0, 1}, {4, 4, 4, 0, 0}};
         } else {
             // radius 4: the y halo through LDS (ylds) loads 2R rows per tile
             // instead of 2R per wave
@@ -442,11 +442,11 @@ void build_candidates(st_plan_s* p) {
                 }
             }
         }
-        // measured on MI355X (512^3, radius 1, 24 steps): four fused steps of
-        // the pipeline for FP64 and FP32 (1032 and 1572 Gcell/s; three: 916
-        // and 1497); bfloat16 storage halves the bytes, so one step already
-        // runs near the HBM rate (1380 Gcell/s)
-        const int want = (p->radius == 1 && p->dtype != kBF16) ? 4 : 1;
+        // measured on MI355X (512^3, radius 1, 100 steps): four fused steps of
+        // the pipeline for FP64 and FP32 (1034-1066 and 1581 Gcell/s; three:
+        // 855 and 1483); bfloat16 three (1627; four: 1523; one step of the
+        // queued-plane kernel: 1384)
+        const int want = p->radius == 1 ? (p->dtype == kBF16 ? 3 : 4) : 1;
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
             return (a.tb == want && a.chunk == 0) > (b.tb == want && b.chunk == 0);
         });
