@@ -234,8 +234,10 @@ st_status stencil_run_noalloc(st_plan plan, void* grid, const double* coeffs, co
  *   flux    device pointer to ONE double; the outflow of the `steps` steps
  *           (each step's sum over the state it reads, weights rounded to the
  *           compute precision, products and sums in FP64 -- except that the
- *           fused FP32-compute kernels add the up to 4 rows of one x-face
- *           column that a lane holds in FP32 first) is ADDED to it.
+ *           fused FP32-compute 3D kernels first add, in FP32, the values of
+ *           one x-face column that a lane holds: up to 4 rows of one state,
+ *           or of the up to 4 states of one plane in the pipelined tiling) is
+ *           ADDED to it.
  *           Under the periodic rule nothing leaves and *flux is not touched.
  *   other arguments as for stencil_run; the grid ends bit-identical to
  *           stencil_run's.

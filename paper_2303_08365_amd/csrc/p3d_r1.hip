@@ -10,6 +10,7 @@ static const Entry3 kTable[] = {
     P3D_BC(float, 4, 4, 4, 8, 2, 1), P3D_BC(float, 4, 4, 4, 8, 1, 1), P3D_BC(float, 4, 4, 3, 8, 2, 1),
     P3D_BC(float, 3, 4, 4, 8, 2, 1),
     P3D_BC(bf16s, 4, 4, 4, 8, 2, 1), P3D_BC(bf16s, 3, 4, 4, 8, 2, 1),
+    P3D_FLUX(double, 4, 2, 4, 8, 2, 1), P3D_FLUX(float, 4, 4, 4, 8, 2, 1), P3D_FLUX(bf16s, 3, 4, 4, 8, 2, 1),
 };
 }  // namespace p3d
 

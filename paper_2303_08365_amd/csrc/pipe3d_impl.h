@@ -57,13 +57,14 @@ namespace st {
 
 namespace p3d {
 
-template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD>
+template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD, bool FLX>
 struct Pipe {
     using S = Storage<TS>;
     using TC = typename S::TC;
     static_assert(NW >= 2 && K >= 2, "a tile needs two waves of two rows");
     static_assert(NB == 1 || NB == 2, "one or two LDS buffers");
     static_assert(PD >= 1 && PD <= 2, "one or two planes prefetched");
+    static_assert(!FLX || !PER, "outflow: zero rule only (a periodic grid has no boundary)");
     static constexpr int W = 64 * VX;
     static constexpr int H = NW * K;
     // LDS rows of one level: slot 0 the tile's halo row above, 2w+1 and 2w+2
@@ -90,6 +91,13 @@ struct Pipe {
         int hslot;             // the halo row's LDS slot
         int lane, wave;
         TC w[7];
+        // FLX: the outflow of the owned cells of every state a step reads
+        double* fpart;         // this wave's partial sum
+        int32_t ny, nx, xl, yw, ox0, ox1, oy0, oy1;
+        bool fx;               // the output tile reaches the x faces
+        bool fzy;              // the z chunk reaches a z face, or the wave owns a y-face row
+        int32_t k0, k1;        // the wave's rows that the tile owns: k0 <= k < k1
+        bool rows_all;         // all of them
     };
 
     static __device__ __forceinline__ bool zghost(int32_t z, int32_t nz) {
@@ -149,12 +157,118 @@ struct Pipe {
         ldrow(r, c.ho, h);
     }
 
+    // Outflow (FLX, zero rule, reading of the absorbing ghost layer): a step
+    // moves w_p u(c) from c to c - off_p; what would land outside the grid
+    // has left.  For the 7-point star a face cell loses, per face it lies on,
+    // the weight of the point that looks across that face: z = 0 -> w6,
+    // z = nz-1 -> w1, y = 0 -> w5, y = ny-1 -> w2, x = 0 -> w4, x = nx-1 -> w3.
+    // z and y parts: FP64 per cell, behind wave-uniform branches (nonzero
+    // only on the first / last plane and on the rows of the waves that own a
+    // y-face row).  x part: edge tiles touch the x faces, so a face column is
+    // column 0 of lane 0 or column VX-1 of lane 63; per iteration a lane adds
+    // up those two columns over its owned rows of every state (T_b * K values,
+    // compute precision) and adds the sums to two FP64 totals, weighted once
+    // at the end.
+    static __device__ __forceinline__ double leave_z(const Ctx& c, int32_t z) {
+        return (z + 1 >= c.nz ? static_cast<double>(c.w[1]) : 0.0) + (z < 1 ? static_cast<double>(c.w[6]) : 0.0);
+    }
+    static __device__ __forceinline__ double leave_y(const Ctx& c, int32_t y) {
+        return (y + 1 >= c.ny ? static_cast<double>(c.w[2]) : 0.0) + (y < 1 ? static_cast<double>(c.w[5]) : 0.0);
+    }
+    static __device__ __forceinline__ double leave_x(const Ctx& c, int32_t x) {
+        return (x + 1 >= c.nx ? static_cast<double>(c.w[3]) : 0.0) + (x < 1 ? static_cast<double>(c.w[4]) : 0.0);
+    }
+    static __device__ __forceinline__ bool own_x(const Ctx& c, int32_t x) {
+        return static_cast<uint32_t>(x - c.ox0) < static_cast<uint32_t>(c.ox1 - c.ox0);
+    }
+    struct Flux {
+        double fl;     // z and y parts so far
+        double xa[2];  // owned-row totals of the lane's first and last column
+    };
+    // z and y parts of one plane of one state
+    static __device__ __forceinline__ void flux_zy(const Ctx& c, Flux& f, int32_t z, const TC (&v)[K][VX]) {
+        if (static_cast<uint32_t>(z - c.zs) >= static_cast<uint32_t>(c.ze - c.zs)) return;
+        const bool zb = z < 1 || z + 1 >= c.nz;
+        const double cz = zb ? leave_z(c, z) : 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int32_t y = c.yw + k;
+            if (static_cast<uint32_t>(y - c.oy0) >= static_cast<uint32_t>(c.oy1 - c.oy0)) continue;
+            const bool yb = y < 1 || y + 1 >= c.ny;
+            if (!zb && !yb) continue;
+            const double czy = yb ? cz + leave_y(c, y) : cz;
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                // opaque copy: keeps the conversion inside this rare branch
+                // (otherwise it is hoisted into every plane)
+                TC u = v[k][e];
+                __asm__ volatile("" : "+v"(u));
+                f.fl = own_x(c, c.xl + e) ? fma(static_cast<double>(u), czy, f.fl) : f.fl;
+            }
+        }
+    }
+    // All states of one iteration (planes zin - l of levels l < TB): the z / y
+    // parts per state; the x part as one compute-precision sum per candidate
+    // column over the owned rows of the states whose plane is owned, added to
+    // the FP64 total once per iteration.
+    template <int TB>
+    static __device__ __forceinline__ void flux_add(const Ctx& c, Flux& f, int32_t zin, const TC (&cur)[TB][K][VX]) {
+        if (c.fzy) {
+#pragma unroll
+            for (int l = 0; l < TB; ++l) flux_zy(c, f, zin - l, cur[l]);
+        }
+        if (c.fx) {
+            if (c.rows_all && zin - (TB - 1) >= c.zs && zin < c.ze) {
+                // every row of every state of this iteration is owned: one
+                // compute-precision sum per column, one FP64 add
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const int e = i == 0 ? 0 : VX - 1;
+                    TC col = cur[0][0][e];
+#pragma unroll
+                    for (int l = 0; l < TB; ++l)
+#pragma unroll
+                        for (int k = (l == 0 ? 1 : 0); k < K; ++k) col += cur[l][k][e];
+                    f.xa[i] += static_cast<double>(col);
+                }
+            } else {
+                // the first and last wave of a tile, the ends of a z chunk:
+                // the owned values one by one, in FP64
+#pragma unroll
+                for (int l = 0; l < TB; ++l) {
+                    const int32_t z = zin - l;
+                    if (static_cast<uint32_t>(z - c.zs) >= static_cast<uint32_t>(c.ze - c.zs)) continue;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        if (k < c.k0 || k >= c.k1) continue;
+#pragma unroll
+                        for (int i = 0; i < 2; ++i) f.xa[i] += static_cast<double>(cur[l][k][i == 0 ? 0 : VX - 1]);
+                    }
+                }
+            }
+        }
+    }
+    static __device__ __forceinline__ void flux_store_sum(const Ctx& c, double t) {
+        t = wave_sum(t);
+        if (c.lane == 0) *c.fpart = t;
+    }
+    static __device__ __forceinline__ void flux_store(const Ctx& c, const Flux& f) {
+        double t = f.fl;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int32_t x = c.xl + (i == 0 ? 0 : VX - 1);
+            t = fma(f.xa[i], own_x(c, x) ? leave_x(c, x) : 0.0, t);
+        }
+        flux_store_sum(c, t);
+    }
+
     template <int TB>
     struct State {
         TC prev[TB][K][VX];   // u_l(z-1)
         TC pend[TB][K][VX];   // P_l(z-1): u_{l+1}(z-1) short of its z+1 term
         TC pf[PD][K][VX];     // prefetched input planes
         TC hpf[PD][VX];       // their halo rows
+        Flux fx;              // FLX only
     };
 
     // One iteration: input plane zin enters level 0.
@@ -192,6 +306,9 @@ struct Pipe {
                 }
             }
         }
+
+        // the states this pass reads, one plane of each: u_l(zin - l)
+        if constexpr (FLX) flux_add<TB>(c, s.fx, zin, cur);
 
         // phase B: edge rows of every level's new plane (and level 0's halo
         // row) through LDS, one barrier
@@ -269,6 +386,8 @@ struct Pipe {
         }
         __syncthreads();
         State<TB> s;
+        s.fx.fl = 0.0;
+        s.fx.xa[0] = s.fx.xa[1] = 0.0;
 #pragma unroll
         for (int l = 0; l < TB; ++l)
 #pragma unroll
@@ -295,6 +414,7 @@ struct Pipe {
         int32_t base = 0;
         for (; base + PD <= nit; base += PD) group<TB>(c, base, zfirst, s, lds, std::make_integer_sequence<int, PD>{});
         tail<TB>(c, base, nit, zfirst, s, lds, std::make_integer_sequence<int, PD>{});
+        if constexpr (FLX) flux_store(c, s.fx);
     }
 
     static __device__ __forceinline__ void run(const Stream3DArgs& a, TC* lds) {
@@ -303,7 +423,11 @@ struct Pipe {
         c.wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
         const uint32_t tiles = static_cast<uint32_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
         const uint32_t item = static_cast<uint32_t>(xcd_remap(blockIdx.x, gridDim.x));
-        if (item >= tiles) return;
+        if constexpr (FLX) c.fpart = a.flux_part + static_cast<int64_t>(blockIdx.x) * NW + c.wave;
+        if (item >= tiles) {
+            if constexpr (FLX) flux_store_sum(c, 0.0);
+            return;
+        }
         const uint32_t txy = item / static_cast<uint32_t>(a.tiles_x);
         const int32_t tx = static_cast<int32_t>(item - txy * a.tiles_x);
         const int32_t ty = static_cast<int32_t>(txy % static_cast<uint32_t>(a.tiles_y));
@@ -345,6 +469,27 @@ struct Pipe {
         }
         c.zs = cz * a.chunk_z;
         c.ze = c.zs + a.chunk_z < c.nz ? c.zs + a.chunk_z : c.nz;
+        if constexpr (FLX) {
+            c.ny = ny;
+            c.nx = nx;
+            c.xl = xl;
+            c.yw = yw;
+            c.ox0 = ox0;
+            c.ox1 = ox1;
+            c.oy0 = oy0;
+            c.oy1 = oy1;
+            c.fx = ox0 < 1 || ox1 > nx - 1;
+            bool fy = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int32_t y = yw + k;
+                fy = fy || (y >= oy0 && y < oy1 && (y < 1 || y + 1 >= ny));
+            }
+            c.k0 = oy0 - yw > 0 ? oy0 - yw : 0;
+            c.k1 = oy1 - yw < K ? oy1 - yw : K;
+            c.rows_all = c.k0 == 0 && c.k1 == K;
+            c.fzy = fy || c.zs < 1 || c.ze > c.nz - 1;
+        }
 #pragma unroll
         for (int p = 0; p < 7; ++p) c.w[p] = static_cast<TC>(a.w[p]);
         const int tb = a.tb;
@@ -355,26 +500,26 @@ struct Pipe {
     }
 };
 
-template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD>
+template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD, bool FLX>
 __global__ __launch_bounds__(64 * NW) void pipe3d_kernel(const Stream3DArgs a) {
-    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD>;
+    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX>;
     extern __shared__ __align__(16) unsigned char smem[];
     P::run(a, reinterpret_cast<typename P::TC*>(smem));
 }
 
-template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD>
+template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD, bool FLX>
 void launch(const Stream3DArgs& a, hipStream_t s) {
-    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD>;
+    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX>;
     const int64_t tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
-    hipLaunchKernelGGL((pipe3d_kernel<TS, TBMAX, VX, K, NW, PER, NB, PD>), dim3(static_cast<unsigned>(tiles)),
+    hipLaunchKernelGGL((pipe3d_kernel<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX>), dim3(static_cast<unsigned>(tiles)),
                        dim3(64 * NW), P::LDS_BYTES, s, a);
 }
 
-template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD>
+template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD, bool FLX>
 int occ_of() {
-    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD>;
+    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX>;
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pipe3d_kernel<TS, TBMAX, VX, K, NW, PER, NB, PD>, 64 * NW,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pipe3d_kernel<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX>, 64 * NW,
                                                      P::LDS_BYTES) != hipSuccess)
         n = 0;
     return n;
@@ -385,13 +530,16 @@ template <> constexpr int32_t dtype_of<double>() { return kF64; }
 template <> constexpr int32_t dtype_of<float>() { return kF32; }
 template <> constexpr int32_t dtype_of<bf16s>() { return kBF16; }
 
-// Key: radius 1, whole-vector rows, pipe = NB * 10 + PD (no late / ylds / flux).
-#define P3D_ENTRY(TS, TBM, VX, K, NW, PER, NB, PD)                                                          \
-    Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, 1, TBM, VX, K, NW, 1, 0, 0, 0, (NB) * 10 + (PD)}, \
-           &launch<TS, TBM, VX, K, NW, PER, NB, PD>, Pipe<TS, TBM, VX, K, NW, PER, NB, PD>::LDS_BYTES,               \
-           &occ_of<TS, TBM, VX, K, NW, PER, NB, PD>}
+// Key: radius 1, whole-vector rows, pipe = NB * 10 + PD (no late / ylds).
+#define P3D_ENTRY(TS, TBM, VX, K, NW, PER, NB, PD, FLX)                                                      \
+    Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, 1, TBM, VX, K, NW, 1, 0, 0, FLX,            \
+                       (NB) * 10 + (PD)},                                                                     \
+           &launch<TS, TBM, VX, K, NW, PER, NB, PD, FLX>, Pipe<TS, TBM, VX, K, NW, PER, NB, PD, FLX>::LDS_BYTES,   \
+           &occ_of<TS, TBM, VX, K, NW, PER, NB, PD, FLX>}
 #define P3D_BC(TS, TBM, VX, K, NW, NB, PD) \
-    P3D_ENTRY(TS, TBM, VX, K, NW, false, NB, PD), P3D_ENTRY(TS, TBM, VX, K, NW, true, NB, PD)
+    P3D_ENTRY(TS, TBM, VX, K, NW, false, NB, PD, false), P3D_ENTRY(TS, TBM, VX, K, NW, true, NB, PD, false)
+// outflow-summing twin (zero rule)
+#define P3D_FLUX(TS, TBM, VX, K, NW, NB, PD) P3D_ENTRY(TS, TBM, VX, K, NW, false, NB, PD, true)
 
 }  // namespace p3d
 }  // namespace st

@@ -596,6 +596,12 @@ std::vector<int> pass_list(int64_t steps, int tb, bool& copy) {
     return v;
 }
 
+// The whole-vector form of a 3D tiling applies to this grid (what
+// launch_pass decides per pass from the same facts).
+bool fast3(const st_plan_s* p, const Candidate& c, bool vec_ok) {
+    return vec_ok && (p->bc == kPeriodic || (p->n[2] >= 64 * c.k3.vx && p->n[1] >= static_cast<int64_t>(c.k3.k) * c.k3.nw));
+}
+
 st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, void* dst,
                       const double* wcan, int tb, bool vec_ok, hipStream_t s, double* fpart = nullptr) {
     hipError_t e = hipSuccess;
@@ -694,13 +700,12 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
         Geo3 g;
         if (!geo3(c, p->n, tb, g)) return fail(ST_ERR_UNSUPPORTED, "3D tiling infeasible");
         Stream3DKey key = c.k3;
-        key.fast = vec_ok && (p->bc == kPeriodic ||
-                              (p->n[2] >= 64 * key.vx && p->n[1] >= static_cast<int64_t>(key.k) * key.nw));
+        key.fast = fast3(p, c, vec_ok) ? 1 : 0;
         key.flux = fpart ? 1 : 0;
-        if (key.pipe && (!key.fast || fpart)) {
-            // the pipeline has whole-vector rows only and no outflow sums: this
-            // pass runs on a queued-plane tiling of the plan (same result bit
-            // for bit)
+        if (key.pipe && (!key.fast || !stream3d_has(key))) {
+            // the pipeline has whole-vector rows only (and outflow twins for
+            // some tilings): this pass runs on a queued-plane tiling of the
+            // plan (same result bit for bit)
             for (const Candidate& o : p->cands)
                 if (o.kernel == ST_KERNEL_STREAM3D && !o.k3.pipe && o.k3.tbmax >= tb)
                     return launch_pass(p, o, src, dst, wcan, tb, vec_ok, s, fpart);
@@ -756,6 +761,7 @@ bool flux_fused(const st_plan_s* p, const Candidate& c) {
     k.flux = 1;
     k.fast = 1;
     if (!stream3d_has(k)) return false;
+    if (c.k3.pipe) return true;  // whole-vector rows only: run_steps checks the grid takes them
     k.fast = 0;
     return stream3d_has(k);
 }
@@ -785,21 +791,47 @@ st_status check_flux_parts(const st_plan_s* p, int64_t need) {
 
 // Run `steps` steps with candidate c: grid -> work -> grid ...  With `flux`
 // (zero rule only), the outflow of every step is also added to flux[0].
-st_status run_steps(st_plan_s* p, const Candidate& c_in, void* grid, void* work, const double* wcan,
+int cand_vx(const st_plan_s* p, const Candidate& c) {
+    return c.kernel == ST_KERNEL_STREAM2D   ? c.k2.vx
+           : c.kernel == ST_KERNEL_STREAM3D ? c.k3.vx
+           : c.kernel == ST_KERNEL_STREAM1D ? kStream1DVX
+           : c.kernel == ST_KERNEL_BOX3D    ? box3d_shape(p->dtype, 1).vx
+                                            : 1;
+}
+
+st_status run_steps(st_plan_s* p, const Candidate& c_sel, void* grid, void* work, const double* wcan,
                     int64_t steps, hipStream_t s, double* flux = nullptr) {
-    const bool fused = flux && flux_fused(p, c_in);
+    // The pipeline has whole-vector rows only: on a grid that does not take
+    // them (too small, unaligned) the run uses the plan's first other
+    // candidate, with its own depth (every candidate gives the same bits; the
+    // list always ends with the one-step kernel).
+    const Candidate* pick = &c_sel;
+    if (c_sel.kernel == ST_KERNEL_STREAM3D && c_sel.k3.pipe) {
+        const bool v0 = (p->n[2] % cand_vx(p, c_sel) == 0) && aligned16(grid) && aligned16(work);
+        if (!fast3(p, c_sel, v0)) {
+            for (const Candidate& o : p->cands)
+                if (!(o.kernel == ST_KERNEL_STREAM3D && o.k3.pipe)) {
+                    pick = &o;
+                    break;
+                }
+        }
+    }
+    const Candidate& c_in = *pick;
+    const int vx = c_in.kernel == ST_KERNEL_STREAM2D   ? c_in.k2.vx
+                   : c_in.kernel == ST_KERNEL_STREAM3D ? c_in.k3.vx
+                   : c_in.kernel == ST_KERNEL_STREAM1D ? kStream1DVX
+                   : c_in.kernel == ST_KERNEL_BOX3D    ? box3d_shape(p->dtype, 1).vx
+                                                       : 1;
+    const bool vec_ok = (p->n[2] % vx == 0) && aligned16(grid) && aligned16(work);
+    // the pipeline's outflow twin has whole-vector rows only
+    const bool fused = flux && flux_fused(p, c_in) &&
+                       !(c_in.kernel == ST_KERNEL_STREAM3D && c_in.k3.pipe && !fast3(p, c_in, vec_ok));
     Candidate c = c_in;
     if (flux && !fused) c.tb = 1;
     const int tb = (c.kernel == ST_KERNEL_NAIVE) ? 1 : c.tb;
     bool copy = false;
     const std::vector<int> passes = pass_list(steps, tb, copy);
     const size_t bytes = static_cast<size_t>(plan_cells(p)) * elem_bytes(p->dtype);
-    const int vx = c.kernel == ST_KERNEL_STREAM2D   ? c.k2.vx
-                   : c.kernel == ST_KERNEL_STREAM3D ? c.k3.vx
-                   : c.kernel == ST_KERNEL_STREAM1D ? kStream1DVX
-                   : c.kernel == ST_KERNEL_BOX3D    ? box3d_shape(p->dtype, 1).vx
-                                                    : 1;
-    const bool vec_ok = (p->n[2] % vx == 0) && aligned16(grid) && aligned16(work);
     void* src = grid;
     void* dst = work;
     FluxBandArgs fb;
