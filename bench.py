@@ -15,9 +15,11 @@ bounded sample of the same workload.  Secondary figures (FP32 on the same
 workload, the batched FP32 ensemble) are reported under "secondary".
 
 Other workloads (--workload): heat2d (2D 5-point FP64 512^2, 100 steps),
-box2d (2D 9-point box FP32 8192^2, 1000 steps, periodic), star25 (3D order-4
-25-point star FP32 512^3, 50 steps, periodic), batch (64 2D 5-point grids,
-sides log-uniform in [256, 4096], 500 steps).
+box2d (2D 9-point box FP32 8192^2, 1000 steps, periodic), box2d25 (2D
+25-point box FP64 8192^2, 100 steps, zero rule), star25 (3D order-4 25-point
+star FP32 512^3, 50 steps, periodic), batch (64 2D 5-point grids, sides
+log-uniform in [256, 4096], 500 steps).  --tiling overlapped|tessellated
+times one 2D tiling of Sec. 4.1's two kinds at a depth (A/B).
 """
 from __future__ import annotations
 
@@ -156,9 +158,29 @@ def _tdt(torch, dtype):
 def _select(args):
     if args.variant >= 0:
         return {"variant": args.variant}
+    if args.tiling != "auto":
+        return {"tiling": args.tiling, "tb": args.tb}
     if args.tb > 0:
         return {"tb": args.tb}
     return None
+
+
+def select_tiling(plan, select):
+    """Apply a selection: a candidate index, a fused depth, or the overlapped
+    or tessellated 2D tiling at a depth (0: the plan's default depth) with
+    the model's chunk."""
+    sel = dict(select)
+    tiling = sel.pop("tiling", None)
+    if tiling is None:
+        plan.select(**sel)
+        return
+    tb = sel.pop("tb", 0) or plan.info()["tb"]
+    want = 1 if tiling == "tessellated" else 0
+    ks = [k for k, c in enumerate(plan.candidates())
+          if c["kernel"] == 1 and c["tessellated"] == want and c["tb"] == tb]
+    if not ks:
+        sys.exit(f"no {tiling} 2D tiling of depth {tb} for this workload")
+    plan.select(variant=ks[0])
 
 
 class Workload:
@@ -183,7 +205,7 @@ def heat3d(torch, st, synth, dtype, select=None, n=512, steps=100, alpha=0.15, f
     # traffic of profiles/ stays matched to the timed kernel)
     w.plan = st.Plan(synth.star_offsets(3, 1), shape, dtype, "zero")
     if select:
-        w.plan.select(**select)
+        select_tiling(w.plan, select)
     w.steps, w.cells, w.dtype = steps, n ** 3, dtype
     w.name = f"3D 7-point heat stencil, {n}^3, {steps} steps, alpha {alpha}, zero boundary"
     w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
@@ -217,7 +239,7 @@ def heat2d(torch, st, synth, dtype, select=None, n=512, steps=100, alpha=0.2):
     # fused depth and chunk length come from the library's autotuner
     w.plan = st.Plan(synth.star_offsets(2, 1), shape, dtype, "zero", graph=True, autotune=select is None)
     if select:
-        w.plan.select(**select)
+        select_tiling(w.plan, select)
     w.steps, w.cells, w.dtype = steps, n * n, dtype
     w.name = f"2D 5-point heat stencil, {n}^2, {steps} steps, alpha {alpha}, zero boundary"
     w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
@@ -240,7 +262,7 @@ def heat1d(torch, st, synth, dtype, select=None, n=10_000_000, steps=1000, alpha
     w.work = torch.empty_like(w.u)
     w.plan = st.Plan(offs, shape, dtype, "zero", autotune=select is None)
     if select:
-        w.plan.select(**select)
+        select_tiling(w.plan, select)
     w.steps, w.cells, w.dtype = steps, n, dtype
     w.name = f"1D {2 * radius + 1}-point star, {n} cells, {steps} steps, zero boundary"
     w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
@@ -258,7 +280,7 @@ def box27(torch, st, synth, dtype, select=None, n=512, steps=20):
     w.work = torch.empty_like(w.u)
     w.plan = st.Plan(synth.box_offsets(3, 1), shape, dtype, "zero", autotune=select is None)
     if select:
-        w.plan.select(**select)
+        select_tiling(w.plan, select)
     w.steps, w.cells, w.dtype = steps, n ** 3, dtype
     w.name = f"3D 27-point box stencil, {n}^3, {steps} steps, zero boundary"
     w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
@@ -274,9 +296,27 @@ def box2d(torch, st, synth, dtype, select=None, n=8192, steps=1000):
     w.work = torch.empty_like(w.u)
     w.plan = st.Plan(synth.box_offsets(2, 1), shape, dtype, "periodic", autotune=select is None)
     if select:
-        w.plan.select(**select)
+        select_tiling(w.plan, select)
     w.steps, w.cells, w.dtype = steps, n * n, dtype
     w.name = f"2D 9-point box stencil (weights 1/9), {n}^2, {steps} steps, periodic"
+    w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
+    w.kernel_tb = w.plan.info()["tb"]
+    return w
+
+
+def box2d25(torch, st, synth, dtype, select=None, n=8192, steps=100):
+    """Tab. 1's Box-2D25P shape class: the 5x5 box, weights 1/25
+    (centre-adjusted), zero rule, U[0,1) seed 0."""
+    w = Workload()
+    shape = (n, n)
+    w.coeffs = list(synth.box_mean_weights(2, 2, "f64" if dtype == "f64" else "f32"))
+    w.u = torch.from_numpy(synth.uniform_field(shape, seed=0)).to("cuda", _tdt(torch, dtype))
+    w.work = torch.empty_like(w.u)
+    w.plan = st.Plan(synth.box_offsets(2, 2), shape, dtype, "zero", autotune=select is None)
+    if select:
+        select_tiling(w.plan, select)
+    w.steps, w.cells, w.dtype = steps, n * n, dtype
+    w.name = f"2D 25-point box stencil (weights 1/25), {n}^2, {steps} steps, zero boundary"
     w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
     w.kernel_tb = w.plan.info()["tb"]
     return w
@@ -290,7 +330,7 @@ def star25(torch, st, synth, dtype, select=None, n=512, steps=50):
     w.work = torch.empty_like(w.u)
     w.plan = st.Plan(synth.star_offsets(3, 4), shape, dtype, "periodic", autotune=select is None)
     if select:
-        w.plan.select(**select)
+        select_tiling(w.plan, select)
     w.steps, w.cells, w.dtype = steps, n ** 3, dtype
     w.name = f"3D order-4 25-point star stencil, {n}^3, {steps} steps, periodic"
     w.run = lambda: w.plan.run(w.u, w.coeffs, w.steps, work=w.work)
@@ -312,7 +352,7 @@ def batch(torch, st, synth, dtype, select=None, ngrids=64, steps=500):
     w.plan = st.BatchPlan(synth.star_offsets(2, 1), shapes, dtype, "zero", autotune=select is None,
                           graph=True)
     if select:
-        w.plan.select(**select)
+        select_tiling(w.plan, select)
     w.steps = steps
     w.cells = int(sum(a * b for a, b in shapes))
     w.dtype = dtype
@@ -416,9 +456,11 @@ def case_study(torch, st, synth, steps, n=9600, mu=0.23, amplitude=100.0, sigma=
     return out
 
 
-WORKLOADS = {"varcoef": varcoef, "heat3d": heat3d, "heat2d": heat2d, "box2d": box2d, "star25": star25, "batch": batch,
+WORKLOADS = {"varcoef": varcoef, "heat3d": heat3d, "heat2d": heat2d, "box2d": box2d, "box2d25": box2d25,
+             "star25": star25, "batch": batch,
              "heat1d": heat1d, "star1d5": lambda *a, **k: heat1d(*a, radius=2, **k), "box27": box27}
-DEFAULT_DTYPE = {"varcoef": "f32", "heat3d": "f64", "heat2d": "f64", "box2d": "f32", "star25": "f32", "batch": "f32",
+DEFAULT_DTYPE = {"varcoef": "f32", "heat3d": "f64", "heat2d": "f64", "box2d": "f32", "box2d25": "f64",
+                 "star25": "f32", "batch": "f32",
                  "heat1d": "f64", "star1d5": "f64", "box27": "f64"}
 KERNEL_NAMES = {0: "naive_kernel", 1: "stream2d_kernel", 2: "stream3d_kernel", 3: "varcoef3d_kernel",
                 4: "stream1d_kernel", 5: "box3d_kernel"}
@@ -442,6 +484,9 @@ def main():
     ap.add_argument("--dtype", default=None, choices=["f64", "f32", "bf16"])
     ap.add_argument("--tb", type=int, default=0, help="force the fused depth (0 = plan default)")
     ap.add_argument("--variant", type=int, default=-1, help="force a tiling candidate")
+    ap.add_argument("--tiling", default="auto", choices=["auto", "overlapped", "tessellated"],
+                    help="2D workloads: time the overlapped or the tessellated tiling (at --tb, else the "
+                         "default depth)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--flux", action="store_true",
@@ -498,7 +543,8 @@ def main():
     info = w.plan.info()
     log(f"plan: {info}")
     tkey = [args.workload, dtype, info["kernel"], info["tb"], info["tile_x"], info["tile_y"], info["tile_z"],
-            info["block"], info["workgroups"], info.get("pipeline", 0)]
+            info["block"], info["workgroups"], info.get("pipeline", 0)] + \
+        ([1] if info.get("tessellated") else [])
     if args.ingest_counters:
         ingest_counters(args.ingest_counters, tkey, os.path.join(args.ingest_counters, "traffic.json"))
         return
@@ -525,7 +571,9 @@ def main():
                    "tile": [info["tile_x"], info["tile_y"], info["tile_z"]],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm",
-                     "kernel": "pipe3d_kernel" if info.get("pipeline") else KERNEL_NAMES[info["kernel"]],
+                     "kernel": ("pipe3d_kernel" if info.get("pipeline") else
+                                "stream2d_kernel + tess2d_band_kernel" if info.get("tessellated") else
+                                KERNEL_NAMES[info["kernel"]]),
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "launches_per_step": passes, "avg_launch_us": round(launch_s * 1e6, 2),

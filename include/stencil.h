@@ -106,6 +106,11 @@ typedef struct {
     int32_t pipeline;         /* ST_KERNEL_STREAM3D: 0 = queued planes, else    */
                               /* the partial-sum pipeline (LDS buffers * 10 +   */
                               /* prefetched planes)                            */
+    int32_t tessellated;      /* ST_KERNEL_STREAM2D: 1 = tessellated tiling     */
+                              /* along y (paper Sec. 4.1: triangles, then the   */
+                              /* inverted triangles at the chunk junctions, no  */
+                              /* recomputed rows; two launches per pass and a   */
+                              /* band scratch the plan owns), 0 = overlapped    */
 } st_plan_info;
 
 /*

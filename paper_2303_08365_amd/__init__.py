@@ -50,7 +50,8 @@ class PlanInfo(ctypes.Structure):
                 ("shape_class", ctypes.c_int32), ("tile_x", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("workgroups", ctypes.c_int64), ("lds_bytes", ctypes.c_int64),
-                ("variant", ctypes.c_int32), ("ncandidates", ctypes.c_int32), ("pipeline", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("ncandidates", ctypes.c_int32), ("pipeline", ctypes.c_int32),
+                ("tessellated", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -59,13 +59,20 @@ struct Stream2DArgs {
                                 // a grid whose schedule has no such pass does nothing)
     int64_t items;              // total (grid, strip, chunk) work items
     double* flux_part;          // outflow variants: one partial sum per work item
+    void* tess;                 // tessellated tiling: the band rows of every row junction
 };
 // Instantiation key for the 2D family.
 struct Stream2DKey {
     int32_t dtype, bc, cls, radius, tbmax, vx;
     int32_t flux;  // also sums the outflow of every step of the pass (zero rule, single grid)
+    int32_t tess;  // tessellated tiling along y (tess2d.hip): stage 1 of a pass (single grid)
 };
 hipError_t launch_stream2d(const Stream2DKey& k, const Stream2DArgs& a, hipStream_t s);
+// Stage 2 of a tessellated pass (tess2d.hip): the inverted triangles at the
+// row junctions, one wave per (junction, strip); `a` as for stage 1.
+hipError_t launch_tess2d_band(const Stream2DKey& k, const Stream2DArgs& a, hipStream_t s);
+// Band rows per junction (both arrays, per strip) of a tessellated pass.
+constexpr int tess_band_rows(int radius, int tb) { return 2 * radius * (tb + 1); }
 bool stream2d_has(const Stream2DKey& k);
 int stream2d_occupancy(const Stream2DKey& k);  // work-groups per CU, 0 if unknown
 

@@ -31,6 +31,7 @@ Table2 s2d_table_f64();
 Table2 s2d_table_f32();
 Table2 s2d_table_bf16();
 Table2 s2d_table_r2();
+Table2 s2d_table_tess();
 Table3 s3d_table_r1_f64();
 Table3 s3d_table_r1_f32();
 Table3 s3d_table_r1_bf16();

@@ -5,12 +5,12 @@ namespace st {
 
 namespace {
 const Entry2* find2(const Stream2DKey& k) {
-    const Table2 tabs[] = {s2d_table_f64(), s2d_table_f32(), s2d_table_bf16(), s2d_table_r2()};
+    const Table2 tabs[] = {s2d_table_f64(), s2d_table_f32(), s2d_table_bf16(), s2d_table_r2(), s2d_table_tess()};
     for (const Table2& t : tabs)
         for (int i = 0; i < t.n; ++i) {
             const Stream2DKey& e = t.e[i].key;
             if (e.dtype == k.dtype && e.bc == k.bc && e.cls == k.cls && e.radius == k.radius &&
-                e.tbmax == k.tbmax && e.vx == k.vx && e.flux == k.flux)
+                e.tbmax == k.tbmax && e.vx == k.vx && e.flux == k.flux && e.tess == k.tess)
                 return &t.e[i];
         }
     return nullptr;

@@ -184,6 +184,9 @@ struct st_plan_s {
     // work-group), sized for the largest pass of any candidate
     double* flux_part = nullptr;
     int64_t flux_cap = 0;
+    // tessellated 2D candidates: the band scratch, sized for the largest pass
+    void* tess_buf = nullptr;
+    int64_t tess_cap = 0;
     // batch
     bool batch = false;
     std::vector<BatchGrid> grids;
@@ -248,6 +251,29 @@ int64_t wave_capacity2(const Candidate& c) { return static_cast<int64_t>(device_
 
 bool geo2(const Candidate& c, int64_t ny, int64_t nx, int tb, Geo2& g, int64_t chunk_override = 0) {
     const int vx = c.k2.vx, R = c.k2.radius;
+    if (c.k2.tess) {
+        // Tessellated along y: chunks without halo rows, at least one band
+        // (2R(tb+1) rows) long so the two junction bands of a chunk never
+        // meet; the last chunk takes the remainder.  The band stage has no
+        // ring columns, so its level l is exact l*R columns in from each side.
+        const int64_t band = tess_band_rows(R, tb);
+        g.hxa = static_cast<int32_t>(round_up(static_cast<int64_t>(R) * tb, vx));
+        g.out_w = 64 * vx - 2 * g.hxa;
+        if (g.out_w <= 0) return false;
+        if (c.k2.bc == kPeriodic && ny < band) return false;  // one chunk wraps onto itself
+        g.tiles_x = static_cast<int32_t>(ceil_div(nx, g.out_w));
+        int64_t chunk = chunk_override > 0 ? chunk_override : c.chunk;
+        // the junction's band costs about 4R*tb row transfers (captured
+        // states out, then in again) where the overlapped tiling re-reads
+        // 2R*tb rows
+        if (chunk <= 0) chunk = pick_chunk(ny, g.tiles_x, wave_capacity2(c), 4 * static_cast<int64_t>(R) * tb, band);
+        chunk = std::max<int64_t>(chunk, band);
+        const int64_t chunks = std::max<int64_t>(1, ny / chunk);
+        g.chunk_y = static_cast<int32_t>(ny / chunks);
+        g.chunks_y = static_cast<int32_t>(chunks);
+        g.items = static_cast<int64_t>(g.tiles_x) * g.chunks_y;
+        return g.items < (int64_t(1) << 31);
+    }
     g.hxa = static_cast<int32_t>(round_up(static_cast<int64_t>(R) * (tb - 1), vx));
     g.out_w = 64 * vx - 2 * g.hxa;
     if (g.out_w <= 0) return false;
@@ -261,6 +287,14 @@ bool geo2(const Candidate& c, int64_t ny, int64_t nx, int tb, Geo2& g, int64_t c
     g.chunks_y = static_cast<int32_t>(ceil_div(ny, chunk));
     g.items = static_cast<int64_t>(g.tiles_x) * g.chunks_y;
     return true;
+}
+
+// Band scratch of one tessellated pass: per row junction (indexed by the
+// chunk below it) and strip, the top and pen arrays of 2R(tb+1) rows of
+// 64*VX cells.
+int64_t tess_bytes(const Candidate& c, const Geo2& g, int tb, int dtype) {
+    return static_cast<int64_t>(g.chunks_y) * g.tiles_x * 2 * tess_band_rows(c.k2.radius, tb) * 64 * c.k2.vx *
+           elem_bytes(dtype);
 }
 
 struct Geo1 {
@@ -390,6 +424,23 @@ void build_candidates(st_plan_s* p) {
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
             return (a.tb == want && a.chunk == 0) > (b.tb == want && b.chunk == 0);
         });
+        // the tessellated tiling (no recomputed halo rows, a band stage per
+        // pass) as further candidates of single-grid plans
+        if (!p->batch) {
+            for (int tb : {2, 4, 1, 3})
+                for (int ch : {0, 64, 128, 256}) {
+                    Candidate c;
+                    c.kernel = ST_KERNEL_STREAM2D;
+                    c.tb = tb;
+                    c.chunk = ch;
+                    c.k2 = Stream2DKey{p->dtype, p->bc, p->cls, p->radius, 4, vx, 0, 1};
+                    if (!stream2d_has(c.k2)) continue;
+                    if (ch > 0 && ch >= p->n[1]) continue;
+                    if (have_device()) c.occ = stream2d_occupancy(c.k2);
+                    Geo2 g;
+                    if (geo2(c, p->n[1], p->n[2], tb, g)) fast.push_back(c);
+                }
+        }
     }
     if (!force_naive && p->ndim == 3 && p->cls == kStar && (p->radius == 1 || p->radius == 4)) {
         // ylds: step-0 y neighbours through LDS, the tile's halo rows loaded once
@@ -687,6 +738,21 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
         G.tile_begin = 0;
         for (int i = 0; i < p->npoints; ++i) G.w[i] = wcan[i];
         Stream2DKey key = c.k2;
+        if (key.tess) {
+            // stage 1 (triangles) then stage 2 (inverted triangles at the
+            // junctions), in stream order; outflow runs never take this form
+            if (fpart) return fail(ST_ERR_UNSUPPORTED, "the tessellated tiling has no outflow twin");
+            const int64_t need = tess_bytes(c, g, tb, p->dtype);
+            if (!p->tess_buf || need > p->tess_cap)
+                return fail(ST_ERR_UNSUPPORTED, "a tessellated pass needs %lld bytes of band scratch, the plan holds %lld",
+                            static_cast<long long>(need), static_cast<long long>(p->tess_cap));
+            a.tess = p->tess_buf;
+            e = launch_stream2d(key, a, s);
+            if (e != hipSuccess) return hip_fail(e, "stream2d launch (tessellated stage 1)");
+            e = launch_tess2d_band(key, a, s);
+            if (e != hipSuccess) return hip_fail(e, "tess2d band launch");
+            return ST_OK;
+        }
         if (fpart) {
             key.flux = 1;
             if (!stream2d_has(key)) key.tbmax = 8;  // the deepest twin runs any depth
@@ -750,6 +816,7 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
 bool flux_fused(const st_plan_s* p, const Candidate& c) {
     if (p->bc != kZero) return false;
     if (c.kernel == ST_KERNEL_STREAM2D) {
+        if (c.k2.tess) return false;
         Stream2DKey k = c.k2;
         k.flux = 1;
         if (stream2d_has(k)) return true;
@@ -892,6 +959,7 @@ void describe(const st_plan_s* p, const Candidate& c, int index, st_plan_info* i
         info->tile_z = 1;
         info->block = 256;
         info->workgroups = ceil_div(g.items, 4);
+        info->tessellated = c.k2.tess;
     } else if (c.kernel == ST_KERNEL_BOX3D) {
         GeoB g;
         geob(p, c, c.tb, g);
@@ -1183,6 +1251,7 @@ st_status stencil_plan_destroy(st_plan plan) {
     if (!plan) return ST_OK;
     if (plan->owned_work) hipFree(plan->owned_work);
     if (plan->flux_part) hipFree(plan->flux_part);
+    if (plan->tess_buf) hipFree(plan->tess_buf);
     if (plan->table_dev) hipFree(plan->table_dev);
     if (plan->mirror) stencil_plan_destroy(plan->mirror);
     if (plan->graph_exec) hipGraphExecDestroy(plan->graph_exec);
@@ -1630,6 +1699,22 @@ st_status plan_buffers(st_plan_s* p) {
             return fail(ST_ERR_NOMEM, "hipMalloc of %lld outflow partial sums failed", static_cast<long long>(need));
         }
         p->flux_cap = need;
+    }
+    int64_t tess = 0;
+    for (const Candidate& c : p->cands) {
+        if (c.kernel != ST_KERNEL_STREAM2D || !c.k2.tess) continue;
+        for (int t = 1; t <= c.tb; ++t) {
+            Geo2 g;
+            if (geo2(c, p->n[1], p->n[2], t, g)) tess = std::max(tess, tess_bytes(c, g, t, p->dtype));
+        }
+    }
+    if (tess > 0) {
+        if (hipMalloc(&p->tess_buf, static_cast<size_t>(tess)) != hipSuccess) {
+            p->tess_buf = nullptr;
+            return fail(ST_ERR_NOMEM, "hipMalloc(%lld) for the tessellated band scratch failed",
+                        static_cast<long long>(tess));
+        }
+        p->tess_cap = tess;
     }
     if (p->batch) {
         const size_t bytes = p->grids.size() * sizeof(Stream2DGrid);

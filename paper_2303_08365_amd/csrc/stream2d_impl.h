@@ -47,7 +47,7 @@ namespace st {
 
 namespace s2d {
 
-template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER, bool FLX>
+template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER, bool FLX, bool TESS = false>
 struct Kern {
     using S = Storage<TS>;
     using TC = typename S::TC;
@@ -77,6 +77,13 @@ struct Kern {
         double* fpart;          // FLX: this wave's partial outflow slot
         bool fx;                // FLX: the strip owns a column within R of an x face
         bool fyb;               // FLX: the chunk owns a row within R of a y face
+        // TESS: rows [cs, ce) of the chunk; a junction with the neighbouring
+        // chunk above (jlo) / below (jhi) and its index; the band scratch
+        int32_t cs, ce;
+        bool jlo, jhi;
+        int32_t jlo_idx, jhi_idx;
+        TS* tess;
+        int32_t tiles_x, tx;
     };
 
     static __device__ __forceinline__ bool ghost(int32_t i, int32_t n) {
@@ -339,6 +346,47 @@ struct Kern {
         if (c.lane == 0) *c.fpart = t;
     }
 
+    // Tessellated tiling along y (paper Sec. 4.1: triangles, then inverted
+    // triangles from two halves of neighbouring triangles).  A chunk streams
+    // only its own rows, so state s of row y is exact only at distance
+    // >= R*s from a junction (a chunk boundary shared with another chunk);
+    // the row's last exact state is L = min(T_b, d / R).  Rows with L = T_b
+    // are stored as usual; for the others the two highest exact states (L and
+    // L - 1: "top" and "pen") go to the junction's band scratch, where stage 2
+    // (tess2d.hip) finishes them.  State s of row y is kept when its distance
+    // d lies in [R*s, R*s + 2R): top when d < R*(s + 1), pen otherwise.
+    // Scratch: [junction][strip][top, pen][band row b][W], band row b of
+    // junction J is grid row J - R*(T_b + 1) + b.
+    template <int TB, int SL>
+    static __device__ __forceinline__ void tess_capture(const Ctx& c, int32_t y, const TC (&v)[VX]) {
+        constexpr int BR = tess_band_rows(R, TB);
+        const int32_t dlo = y - c.cs, dhi = c.ce - 1 - y;
+        int32_t j = -1, b = 0, arr = 0;
+        if (c.jlo && dlo >= R * SL && dlo < R * (SL + 2)) {
+            j = c.jlo_idx;
+            b = R * (TB + 1) + dlo;
+            arr = dlo < R * (SL + 1) ? 0 : 1;
+        } else if (c.jhi && dhi >= R * SL && dhi < R * (SL + 2)) {
+            j = c.jhi_idx;
+            b = R * (TB + 1) - 1 - dhi;
+            arr = dhi < R * (SL + 1) ? 0 : 1;
+        }
+        if (j < 0) return;
+        TS* row = c.tess + (((static_cast<int64_t>(j) * c.tiles_x + c.tx) * 2 + arr) * BR + b) * W;
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc(row, 0, static_cast<uint32_t>(W * sizeof(TS)), kRsrcWord3);
+        bstorev(r, static_cast<uint32_t>(c.lane * VX * sizeof(TS)), v);
+    }
+
+    // level index of an unrolled loop to the template argument
+    template <int TB, int SL = 1>
+    static __device__ __forceinline__ void tess_capture_l(const Ctx& c, int sl, int32_t y, const TC (&v)[VX]) {
+        if constexpr (SL < TB) {
+            if (sl == SL) tess_capture<TB, SL>(c, y, v);
+            else tess_capture_l<TB, SL + 1>(c, sl, y, v);
+        }
+    }
+
     static __device__ __forceinline__ int32_t next_row(const Ctx& c, int32_t y) {
         if constexpr (PER) return y + 1 == c.ny ? 0 : y + 1;
         return y + 1;
@@ -351,6 +399,7 @@ struct Kern {
         for (int e = 0; e < VX; ++e) s.q[0][J][e] = s.pf[J][e];
         s.xq[J] = s.pfx[J];
         if constexpr (FLX) flux_add<TB, FAST>(c, s, yin, s.q[0][J]);  // the pass's input state
+        if constexpr (TESS) tess_capture<TB, 0>(c, yin, s.q[0][J]);
         // rows past the end of the stream are never consumed: load the last
         // streamed row again (a cache hit)
         load_row<FAST>(c, yin + Q <= c.ylast ? s.yl : c.ylast_w, s.pf[J], s.pfx[J]);
@@ -366,6 +415,7 @@ struct Kern {
             } else {
                 finish<FAST>(c, yc, out);
                 if constexpr (FLX) flux_add<TB, FAST>(c, s, yc, out);  // state after step l
+                if constexpr (TESS) tess_capture_l<TB>(c, l + 1, yc, out);
 #pragma unroll
                 for (int e = 0; e < VX; ++e) s.q[l + 1][J][e] = out[e];
             }
@@ -389,8 +439,10 @@ struct Kern {
 
     template <int TB, bool FAST>
     static __device__ __forceinline__ void body(Ctx& c) {
-        const int32_t yfirst = c.ys - R * TB;
-        const int32_t nit = (c.ye - c.ys) + 2 * R * TB;
+        // TESS: a junction side streams no halo rows (the triangle); a grid
+        // edge under the zero rule streams the ghost rows as usual
+        const int32_t yfirst = TESS ? (c.jlo ? c.cs : c.cs - R * TB) : c.ys - R * TB;
+        const int32_t nit = TESS ? (c.jhi ? c.ce : c.ce + R * TB) - yfirst : (c.ye - c.ys) + 2 * R * TB;
         c.ylast = yfirst + nit - 1;
         c.ylast_w = wrap_row(c, c.ylast);
         State<TB> s;
@@ -498,6 +550,24 @@ struct Kern {
         c.out_bytes = static_cast<uint32_t>(c.olast - c.ofirst) * sizeof(TS);
         c.ys = cy * chunk_y;
         c.ye = c.ys + chunk_y < c.ny ? c.ys + chunk_y : c.ny;
+        if constexpr (TESS) {
+            // chunks of chunk_y rows, the last one taking the remainder; a
+            // junction between every two chunks (and, periodic, between the
+            // last and the first); rows within R*tb of a junction are
+            // finished by stage 2
+            const int32_t chunks = uni(gp->chunks_y);
+            c.cs = c.ys;
+            c.ce = cy + 1 == chunks ? c.ny : c.ys + chunk_y;
+            c.jlo = PER || cy > 0;
+            c.jhi = PER || cy + 1 < chunks;
+            c.jlo_idx = cy;
+            c.jhi_idx = cy + 1 == chunks ? 0 : cy + 1;
+            c.tess = static_cast<TS*>(a.tess);
+            c.tiles_x = tiles_x;
+            c.tx = tx;
+            c.ys = c.cs + (c.jlo ? R * tb : 0);
+            c.ye = c.ce - (c.jhi ? R * tb : 0);
+        }
 #pragma unroll
         for (int p = 0; p < NP; ++p) c.w[p] = static_cast<TC>(uni(gp->w[p]));
         if constexpr (FLX) {
@@ -510,23 +580,23 @@ struct Kern {
     }
 };
 
-template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER, bool FLX>
+template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER, bool FLX, bool TESS = false>
 __global__ __launch_bounds__(256) void stream2d_kernel(const Stream2DArgs a) {
-    Kern<TS, R, CLS, TBMAX, VX, PER, FLX>::run(a);
+    Kern<TS, R, CLS, TBMAX, VX, PER, FLX, TESS>::run(a);
 }
 
-template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER, bool FLX>
+template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER, bool FLX, bool TESS = false>
 void launch(const Stream2DArgs& a, hipStream_t s) {
     const int64_t wgs = (a.items + 3) / 4;
-    hipLaunchKernelGGL((stream2d_kernel<TS, R, CLS, TBMAX, VX, PER, FLX>), dim3(static_cast<unsigned>(wgs)),
+    hipLaunchKernelGGL((stream2d_kernel<TS, R, CLS, TBMAX, VX, PER, FLX, TESS>), dim3(static_cast<unsigned>(wgs)),
                        dim3(256), 0, s, a);
 }
 
-template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER, bool FLX>
+template <typename TS, int R, int CLS, int TBMAX, int VX, bool PER, bool FLX, bool TESS = false>
 int occ_of() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_kernel<TS, R, CLS, TBMAX, VX, PER, FLX>, 256, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_kernel<TS, R, CLS, TBMAX, VX, PER, FLX, TESS>, 256,
+                                                     0) != hipSuccess)
         n = 0;
     return n;
 }
@@ -537,8 +607,13 @@ template <> constexpr int32_t dtype_of<float>() { return kF32; }
 template <> constexpr int32_t dtype_of<bf16s>() { return kBF16; }
 
 #define S2D_ENTRY(TS, R, CLS, TBM, VX, PER, FLX)                                               \
-    Entry2{Stream2DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, CLS, R, TBM, VX, FLX},       \
+    Entry2{Stream2DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, CLS, R, TBM, VX, FLX, 0},    \
            &launch<TS, R, CLS, TBM, VX, PER, FLX>, &occ_of<TS, R, CLS, TBM, VX, PER, FLX>}
+// stage 1 of the tessellated tiling (stage 2: tess2d.hip)
+#define S2D_TESS_ENTRY(TS, R, CLS, TBM, VX, PER)                                                \
+    Entry2{Stream2DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, CLS, R, TBM, VX, 0, 1},       \
+           &launch<TS, R, CLS, TBM, VX, PER, false, true>, &occ_of<TS, R, CLS, TBM, VX, PER, false, true>}
+#define S2D_TESS(TS, R, CLS, TBM, VX) S2D_TESS_ENTRY(TS, R, CLS, TBM, VX, false), S2D_TESS_ENTRY(TS, R, CLS, TBM, VX, true)
 #define S2D_BC(TS, R, CLS, TBM, VX) \
     S2D_ENTRY(TS, R, CLS, TBM, VX, false, false), S2D_ENTRY(TS, R, CLS, TBM, VX, true, false)
 // outflow-summing variant (radius-1 star, zero rule, single grid)

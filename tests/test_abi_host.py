@@ -86,9 +86,46 @@ def test_candidates_and_select():
 
 def test_fused_tiles_shrink_by_the_halo():
     p = st.Plan(synth.star_offsets(2, 1), (4096, 4096), "f32")
-    by_tb = {c["tb"]: c for c in p.candidates() if c["kernel"] == st.KERNEL_STREAM2D}
+    by_tb = {c["tb"]: c for c in p.candidates() if c["kernel"] == st.KERNEL_STREAM2D and not c["tessellated"]}
     assert by_tb[1]["tile_x"] == 256            # 64 lanes x 4 columns, no halo
     assert by_tb[8]["tile_x"] == 256 - 2 * 8    # halo 7 rounded up to the lane width
+
+
+@pytest.mark.parametrize("dtype,radius,cls,bc", [("f64", 2, "box", "zero"), ("f32", 1, "star", "periodic"),
+                                                 ("f64", 1, "box", "periodic"), ("f32", 2, "star", "zero")])
+def test_tessellated_candidates_geometry(dtype, radius, cls, bc):
+    # Sec. 4.1's two-stage tiling: chunks of at least one junction band
+    # (2R(T_b+1) rows) with no halo rows, and strips whose halo is R*T_b
+    # columns (the band stage has no ring columns), rounded to the lane width
+    offs = synth.star_offsets(2, radius) if cls == "star" else synth.box_offsets(2, radius)
+    ny, nx = 1000, 2000
+    p = st.Plan(offs, (ny, nx), dtype, bc)
+    cands = p.candidates()
+    tess = [c for c in cands if c["tessellated"]]
+    assert tess and not cands[0]["tessellated"]     # an A/B candidate, never the default
+    vx = 2 if dtype == "f64" else 4
+    for c in tess:
+        assert c["kernel"] == st.KERNEL_STREAM2D and 1 <= c["tb"] <= 4
+        hxa = -(-radius * c["tb"] // vx) * vx
+        assert c["tile_x"] == 64 * vx - 2 * hxa
+        band = 2 * radius * (c["tb"] + 1)
+        assert c["tile_y"] >= band
+        chunks = ny // c["tile_y"]
+        assert ny - (chunks - 1) * c["tile_y"] >= c["tile_y"]   # the last chunk takes the remainder
+        tiles_x = -(-nx // c["tile_x"])
+        assert c["workgroups"] == -(-tiles_x * chunks // 4)
+    # a grid shorter than one band: periodic plans offer none (a chunk would
+    # wrap onto its own band), zero-rule plans one chunk with no junction
+    ny_short = 4 * radius - 1                         # below the T_b = 1 band
+    short = [c for c in st.Plan(offs, (ny_short, nx), dtype, bc).candidates() if c["tessellated"]]
+    if bc == "periodic":
+        assert not short
+    else:
+        assert short and all(c["tile_y"] == ny_short for c in short)
+    # batched plans keep the overlapped tiling only
+    if radius == 1:
+        bp = st.BatchPlan(offs, [(64, 64), (100, 80)], dtype, bc)
+        assert bp.info()["tessellated"] == 0
 
 
 def _raw_plan(offsets, shape, dtype=0, bc=0, flags=0):
