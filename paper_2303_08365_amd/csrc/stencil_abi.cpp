@@ -254,10 +254,10 @@ bool geo2(const Candidate& c, int64_t ny, int64_t nx, int tb, Geo2& g, int64_t c
     if (c.k2.tess) {
         // Tessellated along y: chunks without halo rows, at least one band
         // (2R(tb+1) rows) long so the two junction bands of a chunk never
-        // meet; the last chunk takes the remainder.  The band stage has no
-        // ring columns, so its level l is exact l*R columns in from each side.
+        // meet; the last chunk takes the remainder.  x as for the overlapped
+        // tiling (the band stage gets the strips' ring columns with state 0).
         const int64_t band = tess_band_rows(R, tb);
-        g.hxa = static_cast<int32_t>(round_up(static_cast<int64_t>(R) * tb, vx));
+        g.hxa = static_cast<int32_t>(round_up(static_cast<int64_t>(R) * (tb - 1), vx));
         g.out_w = 64 * vx - 2 * g.hxa;
         if (g.out_w <= 0) return false;
         if (c.k2.bc == kPeriodic && ny < band) return false;  // one chunk wraps onto itself
@@ -291,9 +291,9 @@ bool geo2(const Candidate& c, int64_t ny, int64_t nx, int tb, Geo2& g, int64_t c
 
 // Band scratch of one tessellated pass: per row junction (indexed by the
 // chunk below it) and strip, the top and pen arrays of 2R(tb+1) rows of
-// 64*VX cells.
+// 64*VX cells and the rows' ring values (64 per row).
 int64_t tess_bytes(const Candidate& c, const Geo2& g, int tb, int dtype) {
-    return static_cast<int64_t>(g.chunks_y) * g.tiles_x * 2 * tess_band_rows(c.k2.radius, tb) * 64 * c.k2.vx *
+    return static_cast<int64_t>(g.chunks_y) * g.tiles_x * tess_band_rows(c.k2.radius, tb) * (2 * 64 * c.k2.vx + 64) *
            elem_bytes(dtype);
 }
 

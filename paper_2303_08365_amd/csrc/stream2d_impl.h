@@ -77,13 +77,16 @@ struct Kern {
         double* fpart;          // FLX: this wave's partial outflow slot
         bool fx;                // FLX: the strip owns a column within R of an x face
         bool fyb;               // FLX: the chunk owns a row within R of a y face
-        // TESS: rows [cs, ce) of the chunk; a junction with the neighbouring
-        // chunk above (jlo) / below (jhi) and its index; the band scratch
+        // TESS: rows [cs, ce) of the chunk, a junction with the neighbouring
+        // chunk above (jlo) / below (jhi); distances to a junction count
+        // from clo (the chunk's first row) and chi (its last row), set far
+        // away on a side without one; blo / bhi: this strip's band blocks
+        // of the two junctions
         int32_t cs, ce;
         bool jlo, jhi;
-        int32_t jlo_idx, jhi_idx;
-        TS* tess;
-        int32_t tiles_x, tx;
+        int32_t clo, chi;
+        TS* blo;
+        TS* bhi;
     };
 
     static __device__ __forceinline__ bool ghost(int32_t i, int32_t n) {
@@ -352,37 +355,49 @@ struct Kern {
     // >= R*s from a junction (a chunk boundary shared with another chunk);
     // the row's last exact state is L = min(T_b, d / R).  Rows with L = T_b
     // are stored as usual; for the others the two highest exact states (L and
-    // L - 1: "top" and "pen") go to the junction's band scratch, where stage 2
+    // L - 1: "top" and "pen") go to the junction's band block, where stage 2
     // (tess2d.hip) finishes them.  State s of row y is kept when its distance
-    // d lies in [R*s, R*s + 2R): top when d < R*(s + 1), pen otherwise.
-    // Scratch: [junction][strip][top, pen][band row b][W], band row b of
-    // junction J is grid row J - R*(T_b + 1) + b.
+    // d lies in [R*s, R*s + 2R): top when d < R*(s + 1), pen otherwise; a
+    // state-0 row also keeps its ring values (the R columns beyond each end
+    // of the strip), so that stage 2's first step is exact on the whole strip
+    // as stage 1's is.  Band block of (junction, strip): top [BR][W], pen
+    // [BR][W], ring [BR][64]; band row b of junction J is grid row
+    // J - R*(T_b + 1) + b.
     template <int TB, int SL>
-    static __device__ __forceinline__ void tess_capture(const Ctx& c, int32_t y, const TC (&v)[VX]) {
+    static __device__ __forceinline__ void tess_capture(const Ctx& c, int32_t y, const TC (&v)[VX], TC xr) {
         constexpr int BR = tess_band_rows(R, TB);
-        const int32_t dlo = y - c.cs, dhi = c.ce - 1 - y;
-        int32_t j = -1, b = 0, arr = 0;
-        if (c.jlo && dlo >= R * SL && dlo < R * (SL + 2)) {
-            j = c.jlo_idx;
-            b = R * (TB + 1) + dlo;
-            arr = dlo < R * (SL + 1) ? 0 : 1;
-        } else if (c.jhi && dhi >= R * SL && dhi < R * (SL + 2)) {
-            j = c.jhi_idx;
-            b = R * (TB + 1) - 1 - dhi;
-            arr = dhi < R * (SL + 1) ? 0 : 1;
+        constexpr int H = R * (TB + 1);
+        const int32_t dlo = y - c.clo, dhi = c.chi - y;
+        TS* blk;
+        int32_t b, d;
+        if (static_cast<uint32_t>(dlo - R * SL) < static_cast<uint32_t>(2 * R)) {
+            blk = c.blo;
+            b = H + dlo;
+            d = dlo;
+        } else if (static_cast<uint32_t>(dhi - R * SL) < static_cast<uint32_t>(2 * R)) {
+            blk = c.bhi;
+            b = H - 1 - dhi;
+            d = dhi;
+        } else {
+            return;
         }
-        if (j < 0) return;
-        TS* row = c.tess + (((static_cast<int64_t>(j) * c.tiles_x + c.tx) * 2 + arr) * BR + b) * W;
+        TS* row = blk + ((d < R * (SL + 1) ? 0 : BR) + b) * W;
         const __amdgpu_buffer_rsrc_t r =
             __builtin_amdgcn_make_buffer_rsrc(row, 0, static_cast<uint32_t>(W * sizeof(TS)), kRsrcWord3);
         bstorev(r, static_cast<uint32_t>(c.lane * VX * sizeof(TS)), v);
+        if constexpr (SL == 0) {
+            TS* ring = blk + 2 * BR * W + b * 64;
+            const __amdgpu_buffer_rsrc_t rr =
+                __builtin_amdgcn_make_buffer_rsrc(ring, 0, static_cast<uint32_t>(64 * sizeof(TS)), kRsrcWord3);
+            bstore1(rr, static_cast<uint32_t>(c.lane * sizeof(TS)), xr);
+        }
     }
 
     // level index of an unrolled loop to the template argument
     template <int TB, int SL = 1>
     static __device__ __forceinline__ void tess_capture_l(const Ctx& c, int sl, int32_t y, const TC (&v)[VX]) {
         if constexpr (SL < TB) {
-            if (sl == SL) tess_capture<TB, SL>(c, y, v);
+            if (sl == SL) tess_capture<TB, SL>(c, y, v, TC(0));
             else tess_capture_l<TB, SL + 1>(c, sl, y, v);
         }
     }
@@ -392,14 +407,16 @@ struct Kern {
         return y + 1;
     }
 
-    template <int TB, bool FAST, int J>
+    // CAP: the iteration may capture band rows (TESS: only the first 2R*T_b
+    // and the last 2R iterations of a chunk do)
+    template <int TB, bool FAST, int J, bool CAP = TESS>
     static __device__ __forceinline__ void step(const Ctx& c, int32_t it, int32_t yfirst, State<TB>& s) {
         const int32_t yin = yfirst + it;
 #pragma unroll
         for (int e = 0; e < VX; ++e) s.q[0][J][e] = s.pf[J][e];
         s.xq[J] = s.pfx[J];
         if constexpr (FLX) flux_add<TB, FAST>(c, s, yin, s.q[0][J]);  // the pass's input state
-        if constexpr (TESS) tess_capture<TB, 0>(c, yin, s.q[0][J]);
+        if constexpr (TESS && CAP) tess_capture<TB, 0>(c, yin, s.q[0][J], s.xq[J]);
         // rows past the end of the stream are never consumed: load the last
         // streamed row again (a cache hit)
         load_row<FAST>(c, yin + Q <= c.ylast ? s.yl : c.ylast_w, s.pf[J], s.pfx[J]);
@@ -415,17 +432,17 @@ struct Kern {
             } else {
                 finish<FAST>(c, yc, out);
                 if constexpr (FLX) flux_add<TB, FAST>(c, s, yc, out);  // state after step l
-                if constexpr (TESS) tess_capture_l<TB>(c, l + 1, yc, out);
+                if constexpr (TESS && CAP) tess_capture_l<TB>(c, l + 1, yc, out);
 #pragma unroll
                 for (int e = 0; e < VX; ++e) s.q[l + 1][J][e] = out[e];
             }
         }
     }
 
-    template <int TB, bool FAST, int... J>
+    template <int TB, bool FAST, bool CAP, int... J>
     static __device__ __forceinline__ void group(const Ctx& c, int32_t base, int32_t yfirst, State<TB>& s,
                                                  std::integer_sequence<int, J...>) {
-        (step<TB, FAST, J>(c, base + J, yfirst, s), ...);
+        (step<TB, FAST, J, CAP>(c, base + J, yfirst, s), ...);
     }
     template <int TB, bool FAST, int... J>
     static __device__ __forceinline__ void tail(const Ctx& c, int32_t base, int32_t nit, int32_t yfirst,
@@ -462,8 +479,22 @@ struct Kern {
             s.yl = next_row(c, s.yl);
         }
         int32_t base = 0;
-        for (; base + Q <= nit; base += Q)
-            group<TB, FAST>(c, base, yfirst, s, std::make_integer_sequence<int, Q>{});
+        if constexpr (TESS) {
+            // the capture windows: state SL of a row at distance d in
+            // [R*SL, R*SL + 2R) from a junction is made R*SL rows after the
+            // row is loaded, so captures happen only in the first 2R*T_b
+            // iterations (junction above) and the last 2R (junction below)
+            const int32_t head = 2 * R * TB, tail0 = nit - 2 * R;
+            for (; base + Q <= nit && base < head; base += Q)
+                group<TB, FAST, true>(c, base, yfirst, s, std::make_integer_sequence<int, Q>{});
+            for (; base + Q <= tail0; base += Q)
+                group<TB, FAST, false>(c, base, yfirst, s, std::make_integer_sequence<int, Q>{});
+            for (; base + Q <= nit; base += Q)
+                group<TB, FAST, true>(c, base, yfirst, s, std::make_integer_sequence<int, Q>{});
+        } else {
+            for (; base + Q <= nit; base += Q)
+                group<TB, FAST, false>(c, base, yfirst, s, std::make_integer_sequence<int, Q>{});
+        }
         tail<TB, FAST>(c, base, nit, yfirst, s, std::make_integer_sequence<int, Q>{});
         if constexpr (FLX) flux_store<TB, FAST>(c, s);
     }
@@ -560,16 +591,25 @@ struct Kern {
             c.ce = cy + 1 == chunks ? c.ny : c.ys + chunk_y;
             c.jlo = PER || cy > 0;
             c.jhi = PER || cy + 1 < chunks;
-            c.jlo_idx = cy;
-            c.jhi_idx = cy + 1 == chunks ? 0 : cy + 1;
-            c.tess = static_cast<TS*>(a.tess);
-            c.tiles_x = tiles_x;
-            c.tx = tx;
+            constexpr int32_t kFar = -(1 << 29);
+            c.clo = c.jlo ? c.cs : kFar;
+            c.chi = c.jhi ? c.ce - 1 : kFar;
+            // junction j sits above chunk j (periodic: junction 0 also below
+            // the last chunk)
+            const int64_t blk = static_cast<int64_t>(tess_band_rows(R, tb)) * (2 * W + 64);
+            TS* const t0 = static_cast<TS*>(a.tess);
+            c.blo = t0 + (static_cast<int64_t>(cy) * tiles_x + tx) * blk;
+            c.bhi = t0 + (static_cast<int64_t>(cy + 1 == chunks ? 0 : cy + 1) * tiles_x + tx) * blk;
             c.ys = c.cs + (c.jlo ? R * tb : 0);
             c.ye = c.ce - (c.jhi ? R * tb : 0);
         }
 #pragma unroll
-        for (int p = 0; p < NP; ++p) c.w[p] = static_cast<TC>(uni(gp->w[p]));
+        for (int p = 0; p < NP; ++p) {
+            c.w[p] = static_cast<TC>(uni(gp->w[p]));
+            // TESS with many weights (the radius-2 boxes): the weights live
+            // in VGPRs, leaving the scalar registers to the capture code
+            if constexpr (TESS && NP * sizeof(TC) > 96) __asm__ volatile("" : "+v"(c.w[p]));
+        }
         if constexpr (FLX) {
             c.fpart = a.flux_part + item;
             c.fx = c.ofirst < 1 || c.olast > c.nx - 1;

@@ -18,10 +18,13 @@
 // its pen.  Every row's L is known at compile time (it depends only on its
 // place in the band), so the schedule has no run-time tests.
 //
-// x keeps the overlapped strips of the streaming kernel (a halo of hxa >= R
-// T_b columns at each end; zero entering through DPP at the strip's ends;
-// under the zero rule strips at the grid's x edges move inward, where that
-// zero is the ghost layer).
+// x keeps the overlapped strips of the streaming kernel: state 0 of a band
+// row comes with its ring values (the R columns beyond each end of the
+// strip), so the first step is exact on the whole strip and step t on all but
+// (t - 1)R columns at each end, as in stage 1 (a halo of hxa >= R(T_b - 1)
+// columns); deeper steps take zero through DPP at the strip's ends (under the
+// zero rule strips at the grid's x edges move inward, where that zero is the
+// ghost layer).
 #include "stream2d_impl.h"
 
 namespace st {
@@ -44,18 +47,27 @@ struct Band {
         return d / R < TB ? d / R : TB;
     }
 
+    using KK = Kern<TS, R, CLS, TB, VX, PER, false, true>;
+
     static __device__ __forceinline__ void ldrow(const TS* row, int lane, TC (&v)[VX]) {
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<TS*>(row), 0, static_cast<uint32_t>(W * sizeof(TS)), kRsrcWord3);
-        Kern<TS, R, CLS, TB, VX, PER, false, true>::bloadv(r, static_cast<uint32_t>(lane * VX * sizeof(TS)), v);
+        KK::bloadv(r, static_cast<uint32_t>(lane * VX * sizeof(TS)), v);
     }
 
-    // x neighbours across the lane boundary (zero at the strip's ends)
-    static __device__ __forceinline__ void side(const TC (&v)[VX], TC (&lft)[R], TC (&rgt)[R]) {
+    // x neighbours across the lane boundary: the ring values at the strip's
+    // ends for state 0 (RING), zero for deeper states
+    template <bool RING>
+    static __device__ __forceinline__ void side(const TC (&v)[VX], TC xr, TC (&lft)[R], TC (&rgt)[R]) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            lft[k] = from_lower_z(v[VX - R + k]);
-            rgt[k] = from_upper_z(v[k]);
+            if constexpr (RING) {
+                lft[k] = from_lower(v[VX - R + k], KK::lane_value(xr, k));
+                rgt[k] = from_upper(v[k], KK::lane_value(xr, 32 + k));
+            } else {
+                lft[k] = from_lower_z(v[VX - R + k]);
+                rgt[k] = from_upper_z(v[k]);
+            }
         }
     }
     static __device__ __forceinline__ TC xval(const TC (&v)[VX], const TC (&lft)[R], const TC (&rgt)[R], int idx) {
@@ -65,12 +77,13 @@ struct Band {
     // State t of band row b from the states t - 1 of rows b - R .. b + R,
     // canonical order: centre, then the star's y-, x-, x+, y+ points, or the
     // box's points with (dy, dx) lexicographic.
-    template <int B>
-    static __device__ __forceinline__ void row_step(const TC (&w)[NP], const TC (&v)[BR][VX], TC (&out)[VX]) {
+    template <int B, bool RING>
+    static __device__ __forceinline__ void row_step(const TC (&w)[NP], const TC (&v)[BR][VX], const TC (&xr)[BR],
+                                                    TC (&out)[VX]) {
         static_assert(B - R >= 0 && B + R < BR, "a computed row's neighbours lie in the band");
         if constexpr (CLS == kStar) {
             TC lft[R], rgt[R];
-            side(v[B], lft, rgt);
+            side<RING>(v[B], xr[B], lft, rgt);
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
                 TC acc = w[0] * v[B][e];
@@ -88,7 +101,7 @@ struct Band {
         } else {
             TC lft[2 * R + 1][R], rgt[2 * R + 1][R];
 #pragma unroll
-            for (int dy = -R; dy <= R; ++dy) side(v[B + dy], lft[dy + R], rgt[dy + R]);
+            for (int dy = -R; dy <= R; ++dy) side<RING>(v[B + dy], xr[B + dy], lft[dy + R], rgt[dy + R]);
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
                 TC acc = w[0] * v[B][e];
@@ -120,13 +133,13 @@ struct Band {
     // Level T: rows with L < T computed, rows with L = T take their top, rows
     // with L = T + 1 their pen.
     template <bool FAST, int T, int B = 0>
-    static __device__ __forceinline__ void level_rows(const TC (&w)[NP], const TC (&v)[BR][VX], TC (&nv)[BR][VX],
-                                                      const TS* top, const TS* pen, int lane, int32_t xl,
-                                                      int32_t nx) {
+    static __device__ __forceinline__ void level_rows(const TC (&w)[NP], const TC (&v)[BR][VX], const TC (&xr)[BR],
+                                                      TC (&nv)[BR][VX], const TS* top, const TS* pen, int lane,
+                                                      int32_t xl, int32_t nx) {
         if constexpr (B < BR) {
             constexpr int L = level_of(B);
             if constexpr (L < T) {
-                row_step<B>(w, v, nv[B]);
+                row_step<B, T == 1>(w, v, xr, nv[B]);
                 clear_ghosts<FAST>(xl, nx, nv[B]);
             } else if constexpr (L == T && T < TB) {
                 ldrow(top + B * W, lane, nv[B]);
@@ -136,20 +149,20 @@ struct Band {
 #pragma unroll
                 for (int e = 0; e < VX; ++e) nv[B][e] = v[B][e];
             }
-            level_rows<FAST, T, B + 1>(w, v, nv, top, pen, lane, xl, nx);
+            level_rows<FAST, T, B + 1>(w, v, xr, nv, top, pen, lane, xl, nx);
         }
     }
     template <bool FAST, int T = 1>
-    static __device__ __forceinline__ void levels(const TC (&w)[NP], TC (&v)[BR][VX], const TS* top, const TS* pen,
-                                                  int lane, int32_t xl, int32_t nx) {
+    static __device__ __forceinline__ void levels(const TC (&w)[NP], TC (&v)[BR][VX], const TC (&xr)[BR],
+                                                  const TS* top, const TS* pen, int lane, int32_t xl, int32_t nx) {
         if constexpr (T <= TB) {
             TC nv[BR][VX];
-            level_rows<FAST, T>(w, v, nv, top, pen, lane, xl, nx);
+            level_rows<FAST, T>(w, v, xr, nv, top, pen, lane, xl, nx);
 #pragma unroll
             for (int b = 0; b < BR; ++b)
 #pragma unroll
                 for (int e = 0; e < VX; ++e) v[b][e] = nv[b][e];
-            levels<FAST, T + 1>(w, v, top, pen, lane, xl, nx);
+            levels<FAST, T + 1>(w, v, xr, top, pen, lane, xl, nx);
         }
     }
 
@@ -167,28 +180,32 @@ struct Band {
         TC w[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) w[p] = static_cast<TC>(uni(g.w[p]));
-        const TS* top = static_cast<const TS*>(a.tess) + ((static_cast<int64_t>(j) * tiles_x + tx) * 2 + 0) * BR * W;
-        const TS* pen = top + static_cast<int64_t>(BR) * W;
-        // state 0 of the rows that need it (L = 0: top; L = 1: pen)
-        TC v[BR][VX];
+        const TS* top =
+            static_cast<const TS*>(a.tess) + (static_cast<int64_t>(j) * tiles_x + tx) * (BR * (2 * W + 64));
+        const TS* pen = top + BR * W;
+        const TS* ring = top + 2 * BR * W;
+        // state 0 of the rows that need it (L = 0: top; L = 1: pen), with
+        // its ring values
+        TC v[BR][VX], xr[BR];
 #pragma unroll
         for (int b = 0; b < BR; ++b) {
-            if (level_of(b) == 0) {
-                ldrow(top + b * W, lane, v[b]);
-            } else if (level_of(b) == 1) {
-                ldrow(pen + b * W, lane, v[b]);
+            if (level_of(b) <= 1) {
+                ldrow((level_of(b) == 0 ? top : pen) + b * W, lane, v[b]);
+                const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<TS*>(ring + b * 64), 0, static_cast<uint32_t>(64 * sizeof(TS)), kRsrcWord3);
+                xr[b] = KK::bload1(r, static_cast<uint32_t>(lane * sizeof(TS)));
             } else {
 #pragma unroll
                 for (int e = 0; e < VX; ++e) v[b][e] = TC(0);
+                xr[b] = TC(0);
             }
         }
-        levels<FAST>(w, v, top, pen, lane, xl, nx);
+        levels<FAST>(w, v, xr, top, pen, lane, xl, nx);
         // the rows stage 1 did not finish: L < T_b
         TS* dst = static_cast<TS*>(uni(g.dst));
         const int32_t J = j * chunk_y;
         const uint32_t so = static_cast<uint32_t>(xl - ofirst) * sizeof(TS);
         const uint32_t out_bytes = static_cast<uint32_t>(olast - ofirst) * sizeof(TS);
-        using KK = Kern<TS, R, CLS, TB, VX, PER, false, true>;
 #pragma unroll
         for (int b = 0; b < BR; ++b) {
             if (level_of(b) >= TB) continue;

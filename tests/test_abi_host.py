@@ -95,8 +95,8 @@ def test_fused_tiles_shrink_by_the_halo():
                                                  ("f64", 1, "box", "periodic"), ("f32", 2, "star", "zero")])
 def test_tessellated_candidates_geometry(dtype, radius, cls, bc):
     # Sec. 4.1's two-stage tiling: chunks of at least one junction band
-    # (2R(T_b+1) rows) with no halo rows, and strips whose halo is R*T_b
-    # columns (the band stage has no ring columns), rounded to the lane width
+    # (2R(T_b+1) rows) with no halo rows; strips as for the overlapped tiling
+    # (halo R*(T_b-1) columns rounded to the lane width)
     offs = synth.star_offsets(2, radius) if cls == "star" else synth.box_offsets(2, radius)
     ny, nx = 1000, 2000
     p = st.Plan(offs, (ny, nx), dtype, bc)
@@ -106,7 +106,7 @@ def test_tessellated_candidates_geometry(dtype, radius, cls, bc):
     vx = 2 if dtype == "f64" else 4
     for c in tess:
         assert c["kernel"] == st.KERNEL_STREAM2D and 1 <= c["tb"] <= 4
-        hxa = -(-radius * c["tb"] // vx) * vx
+        hxa = -(-radius * (c["tb"] - 1) // vx) * vx
         assert c["tile_x"] == 64 * vx - 2 * hxa
         band = 2 * radius * (c["tb"] + 1)
         assert c["tile_y"] >= band
