@@ -18,12 +18,23 @@
 // already the finished plane u_{l+1}(z-1) -- it needs no neighbour exchange
 // -- so one iteration first runs that completion through all levels (phase
 // A: level 0's new input plane yields level 1's plane, which yields level
-// 2's, ...; the last level's is stored), then exchanges the edge rows of
-// every level's new plane through LDS behind ONE barrier (phase B), then
-// starts every level's next partial sum (phase C).  Against three queued
-// planes per level and a barrier per level this needs two thirds of the
-// registers and a quarter of the barriers (four fused steps), with the same
-// arithmetic bit for bit.
+// 2's, ...; the last level's is stored), and right behind each completion
+// starts the level's next partial sum with its two terms that need no
+// neighbour, w0 u_l(z) and w1 u_l(z-1); u_l(z) then replaces u_l(z-1), so a
+// level holds two planes at every point of the iteration.  Then the edge
+// rows of every level's new plane go through LDS behind ONE barrier (phase
+// B), and the partial sums take their y and x terms (phase C).  Against
+// three queued planes per level and a barrier per level this needs about
+// two thirds of the registers and a quarter of the barriers (four fused
+// steps), with the same arithmetic bit for bit.
+//
+// Input planes arrive one of two ways.  PD planes ahead in registers: the
+// loads of plane z+PD are issued when plane z enters.  Or (LQ) two planes
+// ahead through a two-slot LDS queue that buffer-to-LDS loads fill: no
+// register holds a plane in flight, the loads have two iterations to land,
+// and a wave reads its rows back from LDS when the plane enters.  Counted on
+// MI355X, the loads' latency is what a pass with one plane ahead in
+// registers waits for.
 //
 // Level l is exact on the register tile shrunk by l columns per side in x
 // (the DPP shifts bring 0 into lanes 0 and 63) and, in y, by l-1 rows per
@@ -57,7 +68,7 @@ namespace st {
 
 namespace p3d {
 
-template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD, bool FLX>
+template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD, bool FLX, bool LQ>
 struct Pipe {
     using S = Storage<TS>;
     using TC = typename S::TC;
@@ -67,6 +78,18 @@ struct Pipe {
     static_assert(!FLX || !PER, "outflow: zero rule only (a periodic grid has no boundary)");
     static constexpr int W = 64 * VX;
     static constexpr int H = NW * K;
+    using TC0 = typename Storage<TS>::TC;
+    // Partial sums started in phase A (early form: two planes a level) or in
+    // phase C (late form: three).  Measured on MI355X at four fused steps:
+    // late is faster for 4 x 2 FP64 values a lane (1075 against 1035
+    // Gcell/s, 512^3), early for 8 x 2 FP32 values (1623 against 1557);
+    // wider FP64 tiles and the LDS queue need early's registers.
+    static constexpr bool kEarly = LQ || sizeof(TC0) < 8 || K * VX > 8;
+    // LQ: the input planes come through a two-slot LDS queue filled by
+    // buffer-to-LDS loads two iterations ahead (no registers held by the
+    // prefetch); one dwordx4 per lane and row, four rows per wave
+    static_assert(!LQ || (VX * sizeof(TS) == 16 && K == 4 && NB == 1 && PD == 2),
+                  "LDS queue: 16-byte rows, four rows per wave, one exchange buffer, two planes ahead");
     // LDS rows of one level: slot 0 the tile's halo row above, 2w+1 and 2w+2
     // the first and last row of wave w, 2*NW+1 the halo row below, 2*NW+2 a
     // sink for waves that own no halo row.  Wave w reads its row above from
@@ -74,7 +97,14 @@ struct Pipe {
     static constexpr int SLOTS = 2 * NW + 3;
     static constexpr int LEVEL_ELEMS = SLOTS * W;
     static constexpr int BUF_ELEMS = TBMAX * LEVEL_ELEMS;
-    static constexpr int LDS_BYTES = NB * BUF_ELEMS * static_cast<int>(sizeof(TC));
+    static constexpr int DYN_BYTES = NB * BUF_ELEMS * static_cast<int>(sizeof(TC));
+    // queue slot: row 0 the halo row above, 1..H the tile's rows, H+1 the
+    // halo row below, H+2 a sink for the waves that own no halo row
+    static constexpr int QROWS = H + 3;
+    static constexpr int QROW_BYTES = W * static_cast<int>(sizeof(TS));
+    static constexpr int QSLOT_BYTES = QROWS * QROW_BYTES;
+    static constexpr int Q_BYTES = LQ ? 2 * QSLOT_BYTES : 16;
+    static constexpr int LDS_BYTES = DYN_BYTES + (LQ ? Q_BYTES : 0);
     static constexpr uint32_t kOut = 0x80000000u;  // past the end of any plane (planes < 2 GiB)
     static constexpr int32_t kRsrcWord3 = 0x00020000;  // gfx9: raw 32-bit data
     static constexpr int kNT = 2;                      // stores: non-temporal
@@ -90,6 +120,11 @@ struct Pipe {
         uint32_t ho;           // same for this wave's halo row; kOut: none, or a ghost row
         int hslot;             // the halo row's LDS slot
         int lane, wave;
+        // LQ: LDS byte address of this lane's 16 bytes of its first row in
+        // queue slot 0, and the queue row its halo load lands in
+        uint32_t qaddr, qhaddr;
+        TS* qbase;             // the queue (slot 0, row 0)
+        int qhrow;
         TC w[7];
         // FLX: the outflow of the owned cells of every state a step reads
         double* fpart;         // this wave's partial sum
@@ -155,6 +190,71 @@ struct Pipe {
 #pragma unroll
         for (int k = 0; k < K; ++k) ldrow(r, c.lo[k], v[k]);
         ldrow(r, c.ho, h);
+    }
+
+    // Workgroup barrier.  LQ: LDS writes drained and the barrier, without
+    // the release fence of __syncthreads, which would also wait for the
+    // queue's loads in flight.  LDS is the only memory the waves exchange.
+    static __device__ __forceinline__ void sync() {
+        if constexpr (LQ) {
+            __asm__ volatile("" ::: "memory");
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt: any
+            __builtin_amdgcn_s_barrier();
+            __asm__ volatile("" ::: "memory");
+        } else {
+            __syncthreads();
+        }
+    }
+    static __device__ __forceinline__ uint32_t lds_addr(const void* p) {
+        return static_cast<uint32_t>(
+            reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) const void*)(p)));
+    }
+    // LQ: plane zin's rows of this wave (and its halo row) into queue slot q,
+    // straight from HBM to LDS; lanes out of a range (ghost plane, ghost
+    // halo row, no halo row) land as 0.  K + 1 loads per wave.
+    static __device__ __forceinline__ void q_issue(const Ctx& c, int q, int32_t zin) {
+        const __amdgpu_buffer_rsrc_t r = plane_in(c, zin);
+        unsigned char* slot = reinterpret_cast<unsigned char*>(c.qbase) + q * QSLOT_BYTES;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                r, (__attribute__((address_space(3))) void*)(slot + (1 + c.wave * K + k) * QROW_BYTES), 16, c.lo[k],
+                0, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            r, (__attribute__((address_space(3))) void*)(slot + c.qhrow * QROW_BYTES), 16, c.ho, 0, 0, 0);
+    }
+    // LQ: this lane's share of queue slot q: its K rows and its halo row.
+    // The loads that filled the slot were issued two iterations ago; every
+    // iteration issues K + 1 queue loads and K stores, so once at most 2K + 1
+    // memory operations are outstanding (the previous iteration's), they are
+    // done.  The compiler sees neither these reads nor this wait, so it adds
+    // no wait of its own for the queue's loads.
+    static __device__ __forceinline__ void q_read(const Ctx& c, int q, TC (&v)[K][VX], TC (&h)[VX]) {
+        const uint32_t a = c.qaddr + q * QSLOT_BYTES;
+        const uint32_t ah = c.qhaddr + q * QSLOT_BYTES;
+        u32x4 r0, r1, r2, r3, rh;
+        __asm__ volatile(
+            "s_waitcnt vmcnt(9)\n\t"
+            "ds_read_b128 %0, %5\n\t"
+            "ds_read_b128 %1, %5 offset:%7\n\t"
+            "ds_read_b128 %2, %5 offset:%8\n\t"
+            "ds_read_b128 %3, %5 offset:%9\n\t"
+            "ds_read_b128 %4, %6\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(rh)
+            : "v"(a), "v"(ah), "n"(QROW_BYTES), "n"(2 * QROW_BYTES), "n"(3 * QROW_BYTES)
+            : "memory");
+        const u32x4 rr[K + 1] = {r0, r1, r2, r3, rh};
+#pragma unroll
+        for (int k = 0; k <= K; ++k) {
+            TS vals[VX];
+            __builtin_memcpy(vals, &rr[k], 16);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                if (k < K) v[k < K ? k : 0][e] = S::widen(vals[e]);
+                else h[e] = S::widen(vals[e]);
+            }
+        }
     }
 
     // Outflow (FLX, zero rule, reading of the absorbing ghost layer): a step
@@ -275,89 +375,138 @@ struct Pipe {
     template <int TB, int J>
     static __device__ __forceinline__ void step(const Ctx& c, int32_t it, int32_t zfirst, State<TB>& s, TC* lds) {
         const int32_t zin = zfirst + it;
-        TC cur[TB][K][VX];
-        TC halo[VX];
+        TC cur[K][VX];  // the new plane of the level at hand: u_l(zin-l)
+        TC* buf = lds + (NB == 2 ? (it & 1) * BUF_ELEMS : 0);
+        if constexpr (LQ) {
+            TC halo[VX];
+            q_read(c, it & 1, cur, halo);
+            TC* lv = buf + c.hslot * W + c.lane * VX;
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+            for (int e = 0; e < VX; ++e) lv[e] = halo[e];
+            q_issue(c, it & 1, zin + 2);  // the slot's reads are done
+        } else {
 #pragma unroll
-            for (int e = 0; e < VX; ++e) cur[0][k][e] = s.pf[J][k][e];
+            for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int e = 0; e < VX; ++e) halo[e] = s.hpf[J][e];
-        load_plane(c, zin + PD, s.pf[J], s.hpf[J]);
+                for (int e = 0; e < VX; ++e) cur[k][e] = s.pf[J][k][e];
+            // Level 0's halo row goes to LDS before the next plane's loads
+            // are issued: its registers are then free to receive them.
+            // (Written later, the halo would stay live across the loads, the
+            // compiler would load into other registers and copy back at the
+            // end of the iteration -- a wait for loads issued in the same
+            // iteration.)  The buffer is free: its last readers passed the
+            // previous barrier.
+            TC* lv = buf + c.hslot * W + c.lane * VX;
+#pragma unroll
+            for (int e = 0; e < VX; ++e) lv[e] = s.hpf[J][e];
+            load_plane(c, zin + PD, s.pf[J], s.hpf[J]);
+        }
 
-        // phase A: u_{l+1}(zin-l-1) = fma(w6, u_l(zin-l), P_l(zin-l-1)); a ghost
-        // plane zin-l (levels >= 1 hold junk there) enters with weight 0
+        // phase A, level by level: u_{l+1}(zin-l-1) = fma(w6, u_l(zin-l),
+        // P_l(zin-l-1)) (a ghost plane zin-l, where levels >= 1 hold junk,
+        // enters with weight 0); the last level's plane is stored.  Early
+        // form: then the next partial sum of level l takes its first two
+        // terms, which need no neighbour, w0 u_l(zin-l) and w1 u_l(zin-l-1),
+        // and u_l(zin-l) replaces u_l(zin-l-1), so across the LDS exchange a
+        // level keeps two planes.  Late form: every level's new plane is kept
+        // (three planes a level) and all of the partial sum waits for phase C,
+        // off the chain of completions that each input plane starts.
+        TC nw[kEarly ? 1 : TB][K][VX];
 #pragma unroll
         for (int l = 0; l < TB; ++l) {
             const TC w6 = (l > 0 && zghost(zin - l, c.nz)) ? TC(0) : c.w[6];
+            TC nxt[K][VX];
             if (l + 1 < TB) {
 #pragma unroll
                 for (int k = 0; k < K; ++k)
 #pragma unroll
-                    for (int e = 0; e < VX; ++e) cur[l + 1][k][e] = S::round(fma_c(w6, cur[l][k][e], s.pend[l][k][e]));
+                    for (int e = 0; e < VX; ++e) nxt[k][e] = S::round(fma_c(w6, cur[k][e], s.pend[l][k][e]));
             } else {
                 const __amdgpu_buffer_rsrc_t r = plane_out(c, zin - TB);
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     TC o[VX];
 #pragma unroll
-                    for (int e = 0; e < VX; ++e) o[e] = fma_c(w6, cur[l][k][e], s.pend[l][k][e]);
+                    for (int e = 0; e < VX; ++e) o[e] = fma_c(w6, cur[k][e], s.pend[l][k][e]);
                     strow(r, c.so[k], o);
                 }
+            }
+            if constexpr (kEarly) {
+                const TC w1 = (l > 0 && zghost(zin - l - 1, c.nz)) ? TC(0) : c.w[1];
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) {
+                        s.pend[l][k][e] = fma_c(w1, s.prev[l][k][e], c.w[0] * cur[k][e]);
+                        s.prev[l][k][e] = cur[k][e];
+                    }
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) nw[kEarly ? 0 : l][k][e] = cur[k][e];
+            }
+            if (l + 1 < TB) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) cur[k][e] = nxt[k][e];
             }
         }
 
         // the states this pass reads, one plane of each: u_l(zin - l)
-        if constexpr (FLX) flux_add<TB>(c, s.fx, zin, cur);
+        if constexpr (FLX) {
+            if constexpr (kEarly) flux_add<TB>(c, s.fx, zin, s.prev);
+            else flux_add<TB>(c, s.fx, zin, nw);
+        }
 
-        // phase B: edge rows of every level's new plane (and level 0's halo
-        // row) through LDS, one barrier
-        TC* buf = lds + (NB == 2 ? (it & 1) * BUF_ELEMS : 0);
+        // phase B: edge rows of every level's new plane through LDS, one
+        // barrier
 #pragma unroll
         for (int l = 0; l < TB; ++l) {
+            const TC (&u)[K][VX] = kEarly ? s.prev[l] : nw[kEarly ? 0 : l];
             TC* lv = buf + l * LEVEL_ELEMS + c.lane * VX;
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                lv[(2 * c.wave + 1) * W + e] = cur[l][0][e];
-                lv[(2 * c.wave + 2) * W + e] = cur[l][K - 1][e];
+                lv[(2 * c.wave + 1) * W + e] = u[0][e];
+                lv[(2 * c.wave + 2) * W + e] = u[K - 1][e];
             }
         }
-        {
-            TC* lv = buf + c.hslot * W + c.lane * VX;
-#pragma unroll
-            for (int e = 0; e < VX; ++e) lv[e] = halo[e];
-        }
-        __syncthreads();
+        sync();
 
-        // phase C: the next partial sums
+        // phase C: the (rest of the) next partial sums; the neighbour rows of
+        // every level are read first, one LDS round trip
+        TC above[TB][VX], below[TB][VX];
 #pragma unroll
         for (int l = 0; l < TB; ++l) {
             const TC* lv = buf + l * LEVEL_ELEMS + c.lane * VX;
-            TC above[VX], below[VX];
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                above[e] = lv[(2 * c.wave) * W + e];
-                below[e] = lv[(2 * c.wave + 3) * W + e];
+                above[l][e] = lv[(2 * c.wave) * W + e];
+                below[l][e] = lv[(2 * c.wave + 3) * W + e];
             }
+        }
+#pragma unroll
+        for (int l = 0; l < TB; ++l) {
+            const TC (&u)[K][VX] = kEarly ? s.prev[l] : nw[kEarly ? 0 : l];
             const TC w1 = (l > 0 && zghost(zin - l - 1, c.nz)) ? TC(0) : c.w[1];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const TC lft = from_lower_z(cur[l][k][VX - 1]);
-                const TC rgt = from_upper_z(cur[l][k][0]);
+                const TC lft = from_lower_z(u[k][VX - 1]);
+                const TC rgt = from_upper_z(u[k][0]);
 #pragma unroll
                 for (int e = 0; e < VX; ++e) {
-                    TC acc = c.w[0] * cur[l][k][e];
-                    acc = fma_c(w1, s.prev[l][k][e], acc);
-                    acc = fma_c(c.w[2], k > 0 ? cur[l][k > 0 ? k - 1 : 0][e] : above[e], acc);
-                    acc = fma_c(c.w[3], e > 0 ? cur[l][k][e > 0 ? e - 1 : 0] : lft, acc);
-                    acc = fma_c(c.w[4], e + 1 < VX ? cur[l][k][e + 1 < VX ? e + 1 : 0] : rgt, acc);
-                    acc = fma_c(c.w[5], k + 1 < K ? cur[l][k + 1 < K ? k + 1 : 0][e] : below[e], acc);
+                    TC acc = kEarly ? s.pend[l][k][e] : fma_c(w1, s.prev[l][k][e], c.w[0] * u[k][e]);
+                    acc = fma_c(c.w[2], k > 0 ? u[k > 0 ? k - 1 : 0][e] : above[l][e], acc);
+                    acc = fma_c(c.w[3], e > 0 ? u[k][e > 0 ? e - 1 : 0] : lft, acc);
+                    acc = fma_c(c.w[4], e + 1 < VX ? u[k][e + 1 < VX ? e + 1 : 0] : rgt, acc);
+                    acc = fma_c(c.w[5], k + 1 < K ? u[k + 1 < K ? k + 1 : 0][e] : below[l][e], acc);
                     s.pend[l][k][e] = acc;
-                    s.prev[l][k][e] = cur[l][k][e];
+                    if constexpr (!kEarly) s.prev[l][k][e] = u[k][e];
                 }
             }
         }
-        if constexpr (NB == 1) __syncthreads();  // the next iteration rewrites the buffer
+        if constexpr (NB == 1) sync();  // the next iteration rewrites the buffer
     }
 
     template <int TB, int... J>
@@ -397,27 +546,35 @@ struct Pipe {
                     s.prev[l][k][e] = TC(0);
                     s.pend[l][k][e] = TC(0);
                 }
+        // stores into an empty range (the hardware drops them): the loop is
+        // then entered, as it is repeated, with each plane's loads followed by
+        // one plane's stores, which the waits at the top of the loop count
+        const __amdgpu_buffer_rsrc_t none = plane_out(c, c.ze);
+        TC zero[VX];
 #pragma unroll
-        for (int p = 0; p < PD; ++p) load_plane(c, zfirst + p, s.pf[p], s.hpf[p]);
-        {
-            // stores into an empty range (the hardware drops them): the loop
-            // is then entered, as it is repeated, with the plane loads followed
-            // by one plane's stores in flight, so the wait for the loads at the
-            // top of the loop need not wait for the stores
-            const __amdgpu_buffer_rsrc_t none = plane_out(c, c.ze);
-            TC zero[VX];
+        for (int e = 0; e < VX; ++e) zero[e] = TC(0);
+        if constexpr (LQ) {
 #pragma unroll
-            for (int e = 0; e < VX; ++e) zero[e] = TC(0);
+            for (int p = 0; p < 2; ++p) {
+                q_issue(c, p, zfirst + p);
+#pragma unroll
+                for (int k = 0; k < K; ++k) strow(none, c.so[k], zero);
+            }
+            for (int32_t it = 0; it < nit; ++it) step<TB, 0>(c, it, zfirst, s, lds);
+        } else {
+#pragma unroll
+            for (int p = 0; p < PD; ++p) load_plane(c, zfirst + p, s.pf[p], s.hpf[p]);
 #pragma unroll
             for (int k = 0; k < K; ++k) strow(none, c.so[k], zero);
+            int32_t base = 0;
+            for (; base + PD <= nit; base += PD)
+                group<TB>(c, base, zfirst, s, lds, std::make_integer_sequence<int, PD>{});
+            tail<TB>(c, base, nit, zfirst, s, lds, std::make_integer_sequence<int, PD>{});
         }
-        int32_t base = 0;
-        for (; base + PD <= nit; base += PD) group<TB>(c, base, zfirst, s, lds, std::make_integer_sequence<int, PD>{});
-        tail<TB>(c, base, nit, zfirst, s, lds, std::make_integer_sequence<int, PD>{});
         if constexpr (FLX) flux_store(c, s.fx);
     }
 
-    static __device__ __forceinline__ void run(const Stream3DArgs& a, TC* lds) {
+    static __device__ __forceinline__ void run(const Stream3DArgs& a, TC* lds, TS* lq) {
         Ctx c;
         c.lane = threadIdx.x & 63;
         c.wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -466,6 +623,13 @@ struct Pipe {
             const int32_t hyw = PER ? wrap_idx(hy, ny) : hy;
             c.ho = valid ? static_cast<uint32_t>(hyw * nx + x0) * sizeof(TS) : kOut;
             c.hslot = top ? 0 : (bot ? 2 * NW + 1 : 2 * NW + 2);
+            if constexpr (LQ) {
+                c.qbase = lq;
+                c.qhrow = top ? 0 : (bot ? H + 1 : H + 2);
+                const uint32_t q0 = lds_addr(lq) + static_cast<uint32_t>(c.lane) * 16u;
+                c.qaddr = q0 + static_cast<uint32_t>((1 + c.wave * K) * QROW_BYTES);
+                c.qhaddr = q0 + static_cast<uint32_t>(c.qhrow * QROW_BYTES);
+            }
         }
         c.zs = cz * a.chunk_z;
         c.ze = c.zs + a.chunk_z < c.nz ? c.zs + a.chunk_z : c.nz;
@@ -500,27 +664,32 @@ struct Pipe {
     }
 };
 
-template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD, bool FLX>
+template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD, bool FLX, bool LQ>
 __global__ __launch_bounds__(64 * NW) void pipe3d_kernel(const Stream3DArgs a) {
-    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX>;
+    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX, LQ>;
     extern __shared__ __align__(16) unsigned char smem[];
-    P::run(a, reinterpret_cast<typename P::TC*>(smem));
+    if constexpr (LQ) {
+        __shared__ __align__(16) unsigned char lq[P::Q_BYTES];
+        P::run(a, reinterpret_cast<typename P::TC*>(smem), reinterpret_cast<TS*>(lq));
+    } else {
+        P::run(a, reinterpret_cast<typename P::TC*>(smem), nullptr);
+    }
 }
 
-template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD, bool FLX>
+template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD, bool FLX, bool LQ>
 void launch(const Stream3DArgs& a, hipStream_t s) {
-    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX>;
+    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX, LQ>;
     const int64_t tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
-    hipLaunchKernelGGL((pipe3d_kernel<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX>), dim3(static_cast<unsigned>(tiles)),
-                       dim3(64 * NW), P::LDS_BYTES, s, a);
+    hipLaunchKernelGGL((pipe3d_kernel<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX, LQ>),
+                       dim3(static_cast<unsigned>(tiles)), dim3(64 * NW), P::DYN_BYTES, s, a);
 }
 
-template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD, bool FLX>
+template <typename TS, int TBMAX, int VX, int K, int NW, bool PER, int NB, int PD, bool FLX, bool LQ>
 int occ_of() {
-    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX>;
+    using P = Pipe<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX, LQ>;
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pipe3d_kernel<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX>, 64 * NW,
-                                                     P::LDS_BYTES) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pipe3d_kernel<TS, TBMAX, VX, K, NW, PER, NB, PD, FLX, LQ>,
+                                                     64 * NW, P::DYN_BYTES) != hipSuccess)
         n = 0;
     return n;
 }
@@ -530,16 +699,21 @@ template <> constexpr int32_t dtype_of<double>() { return kF64; }
 template <> constexpr int32_t dtype_of<float>() { return kF32; }
 template <> constexpr int32_t dtype_of<bf16s>() { return kBF16; }
 
-// Key: radius 1, whole-vector rows, pipe = NB * 10 + PD (no late / ylds).
-#define P3D_ENTRY(TS, TBM, VX, K, NW, PER, NB, PD, FLX)                                                      \
+// Key: radius 1, whole-vector rows, pipe = NB * 10 + PD, plus 100 for the LDS
+// queue (no late / ylds).
+#define P3D_ENTRY(TS, TBM, VX, K, NW, PER, NB, PD, FLX, LQ)                                                  \
     Entry3{Stream3DKey{dtype_of<TS>(), (PER) ? kPeriodic : kZero, 1, TBM, VX, K, NW, 1, 0, 0, FLX,            \
-                       (NB) * 10 + (PD)},                                                                     \
-           &launch<TS, TBM, VX, K, NW, PER, NB, PD, FLX>, Pipe<TS, TBM, VX, K, NW, PER, NB, PD, FLX>::LDS_BYTES,   \
-           &occ_of<TS, TBM, VX, K, NW, PER, NB, PD, FLX>}
+                       (NB) * 10 + (PD) + ((LQ) ? 100 : 0)},                                                  \
+           &launch<TS, TBM, VX, K, NW, PER, NB, PD, FLX, LQ>,                                                 \
+           Pipe<TS, TBM, VX, K, NW, PER, NB, PD, FLX, LQ>::LDS_BYTES, &occ_of<TS, TBM, VX, K, NW, PER, NB, PD, FLX, LQ>}
 #define P3D_BC(TS, TBM, VX, K, NW, NB, PD) \
-    P3D_ENTRY(TS, TBM, VX, K, NW, false, NB, PD, false), P3D_ENTRY(TS, TBM, VX, K, NW, true, NB, PD, false)
-// outflow-summing twin (zero rule)
-#define P3D_FLUX(TS, TBM, VX, K, NW, NB, PD) P3D_ENTRY(TS, TBM, VX, K, NW, false, NB, PD, true)
+    P3D_ENTRY(TS, TBM, VX, K, NW, false, NB, PD, false, false), P3D_ENTRY(TS, TBM, VX, K, NW, true, NB, PD, false, false)
+// the LDS-queue form (one exchange buffer, two planes ahead)
+#define P3D_LQ(TS, TBM, VX, NW) \
+    P3D_ENTRY(TS, TBM, VX, 4, NW, false, 1, 2, false, true), P3D_ENTRY(TS, TBM, VX, 4, NW, true, 1, 2, false, true)
+// outflow-summing twins (zero rule)
+#define P3D_FLUX(TS, TBM, VX, K, NW, NB, PD) P3D_ENTRY(TS, TBM, VX, K, NW, false, NB, PD, true, false)
+#define P3D_LQ_FLUX(TS, TBM, VX, NW) P3D_ENTRY(TS, TBM, VX, 4, NW, false, 1, 2, true, true)
 
 }  // namespace p3d
 }  // namespace st

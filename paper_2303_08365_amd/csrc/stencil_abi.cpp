@@ -447,18 +447,21 @@ void build_candidates(st_plan_s* p) {
         struct V { int vx, k, nw, late, ylds, pipe; };
         std::vector<V> vs;
         if (p->radius == 1) {
-            // first: the fastest measured on MI355X for 512^3 at the default depth
-            // the partial-sum pipeline (pipe = NB*10 + PD) first: with two
-            // LDS buffers it measured 1032 / 1572 Gcell/s (FP64 / FP32, four
-            // fused steps) against 740 / 1394 for the queued-plane kernel
+            // first: the fastest measured on MI355X for 512^3 at the default
+            // depth.  The partial-sum pipeline (pipe = NB*10 + PD, +100 for the
+            // LDS input queue) at four fused steps: FP64 1075 Gcell/s with two
+            // LDS buffers and 4 rows x 128 columns per wave (LDS queue: 955);
+            // FP32 1623 with 8 rows x 128 columns (4 rows x 256 columns: 1530,
+            // LDS queue 1574).  The queued-plane kernel: 740 / 1394.
             if (p->dtype == kF64)
-                vs = {{2, 4, 8, 0, 0, 21}, {2, 4, 8, 1, 1}, {2, 4, 8, 1, 0}, {2, 4, 8, 0, 0}, {2, 4, 4, 0, 0},
-                      {2, 2, 8, 0, 0}, {2, 3, 8, 1, 0}, {2, 4, 8, 0, 1}, {2, 5, 8, 1, 1},
-                      {2, 4, 8, 0, 0, 11}, {2, 3, 8, 0, 0, 21}};
+                vs = {{2, 4, 8, 0, 0, 21}, {2, 4, 8, 0, 0, 112}, {2, 4, 8, 1, 1}, {2, 4, 8, 1, 0},
+                      {2, 4, 8, 0, 0},     {2, 4, 4, 0, 0},      {2, 2, 8, 0, 0}, {2, 3, 8, 1, 0},
+                      {2, 4, 8, 0, 1},     {2, 5, 8, 1, 1},      {2, 4, 8, 0, 0, 11}, {2, 3, 8, 0, 0, 21}};
             else if (p->dtype == kF32)
-                vs = {{4, 4, 8, 0, 0, 21}, {4, 4, 8, 1, 1}, {4, 4, 8, 1, 0}, {4, 4, 8, 0, 0}, {4, 4, 4, 0, 0},
-                      {4, 2, 8, 0, 0}, {4, 3, 8, 1, 0}, {4, 4, 8, 0, 1}, {4, 5, 8, 1, 1},
-                      {4, 4, 8, 0, 0, 11}, {4, 3, 8, 0, 0, 21}};
+                vs = {{2, 8, 8, 0, 0, 21}, {4, 4, 8, 0, 0, 21}, {4, 4, 8, 0, 0, 112}, {4, 4, 8, 1, 1},
+                      {4, 4, 8, 1, 0},     {4, 4, 8, 0, 0},     {4, 4, 4, 0, 0},      {4, 2, 8, 0, 0},
+                      {4, 3, 8, 1, 0},     {4, 4, 8, 0, 1},     {4, 5, 8, 1, 1},      {4, 4, 8, 0, 0, 11},
+                      {4, 3, 8, 0, 0, 21}};
             else
                 vs = {{4, 4, 8, 0, 0, 21}, {4, 4, 8, 0, 1}, {4, 4, 4, 0, 0}};
         } else {
