@@ -70,6 +70,32 @@ def test_3d_heat_outflow_matches_oracle(dtype, shape):
     assert np.array_equal(to_host(g), got)
 
 
+@pytest.mark.parametrize("dtype,shape", [("f64", (19, 70, 300)), ("f32", (14, 70, 520))])
+def test_3d_outflow_every_pipeline_tiling(dtype, shape):
+    # every candidate of the 7-point pipeline (registers or LDS queue, late or
+    # early partial sums, with an outflow twin of its own or standing in for
+    # one): the oracle's outflow, and the grid stencil_run gives, bit for bit
+    import paper_2303_08365_amd as st
+    offs = synth.star_offsets(3, 1)
+    w = synth.heat_weights(3, 0.15, dtype)
+    steps = 9
+    u0 = synth.uniform_field(shape, seed=23)
+    ref, rout = _ref_flux(u0, offs, w, steps, dtype)
+    plan = st.Plan(offs, shape, dtype, "zero")
+    ks = [k for k, c in enumerate(plan.candidates()) if c["kernel"] == 2 and c["pipeline"]]
+    assert any(plan.candidates()[k]["pipeline"] >= 100 for k in ks), "no LDS-queue candidate"
+    for k in ks:
+        c = plan.candidates()[k]
+        print(f"flux pipeline {dtype} {shape} cand {k} tb {c['tb']} pipe {c['pipeline']}", flush=True)
+        plan.select(variant=k)
+        got, out = _run_flux(plan, u0, w, steps, dtype)
+        check(got, ref, dtype, steps, f"cand {k}")
+        _close(out, rout, TOL[dtype], dtype, f"cand {k}")
+        g = to_device(u0, dtype)
+        plan.run(g, list(w), steps)
+        assert np.array_equal(to_host(g), got), f"cand {k}: outflow run and plain run differ"
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("shape", [(24, 61, 530), (20, 40, 520), (300, 1100), (45, 77)])
 def test_fused_and_one_step_outflow_agree(dtype, shape):
