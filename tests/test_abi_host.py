@@ -478,6 +478,32 @@ def _gpu_code_objects(so_path):
         pos = i + len(magic)
 
 
+def test_lds_queue_kernels_keep_their_memory_count():
+    # The 7-point pipeline's LDS-queue form reads its queue slot after an
+    # explicit wait that counts the memory operations of one iteration (K + 1
+    # queue loads, K stores).  A register spill would add scratch operations
+    # to that count: every such kernel must use no scratch, and must load
+    # through the queue (buffer loads into LDS).
+    import re
+    objdump = "/opt/rocm/llvm/bin/llvm-objdump"
+    if not os.path.exists(objdump):
+        pytest.skip("llvm-objdump is not installed")
+    found = 0
+    with tempfile.TemporaryDirectory() as d:
+        for k, b in enumerate(_gpu_code_objects(st.library_path())):
+            f = os.path.join(d, f"co{k}.o")
+            with open(f, "wb") as fh:
+                fh.write(b)
+            dis = subprocess.run([objdump, "-d", f], capture_output=True, text=True, check=True).stdout
+            for m in re.finditer(r"^[0-9a-f]+ <(_Z\w*pipe3d_kernel\w*ELb1EEEvNS_12Stream3DArgsE)>:\n(.*?)(?=^[0-9a-f]+ <|\Z)",
+                                 dis, re.S | re.M):
+                name, body = m.group(1), m.group(2)
+                found += 1
+                assert "scratch_" not in body, f"{name} spills to scratch"
+                assert re.search(r"buffer_load_dwordx4 .* lds", body), f"{name} has no queue loads"
+    assert found >= 4, "no LDS-queue kernel in the library"
+
+
 def test_kernels_contain_no_device_function_calls():
     # Every kernel is inlined into one function that ends in s_endpgm: no
     # device-function call, hence no return address.  An earlier build
