@@ -105,7 +105,8 @@ typedef struct {
     int32_t ncandidates;      /* tiling candidates valid for this plan          */
     int32_t pipeline;         /* ST_KERNEL_STREAM3D: 0 = queued planes, else    */
                               /* the partial-sum pipeline (LDS buffers * 10 +   */
-                              /* prefetched planes)                            */
+                              /* prefetched planes, + 100 when the planes come  */
+                              /* through an LDS queue rather than registers)   */
     int32_t tessellated;      /* ST_KERNEL_STREAM2D: 1 = tessellated tiling     */
                               /* along y (paper Sec. 4.1: triangles, then the   */
                               /* inverted triangles at the chunk junctions, no  */
