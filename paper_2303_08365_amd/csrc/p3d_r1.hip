@@ -17,6 +17,7 @@ static const Entry3 kTable[] = {
     P3D_BC(float, 3, 4, 4, 8, 2, 1),
     P3D_BC(bf16s, 4, 4, 4, 8, 2, 1),
     P3D_BC(bf16s, 3, 4, 4, 8, 2, 1),
+    P3D_BC(bf16s, 3, 4, 6, 8, 2, 1),
     P3D_LQ(double, 4, 2, 8),
     P3D_LQ(float, 4, 4, 8),
     P3D_FLUX(double, 4, 2, 4, 8, 2, 1),

@@ -452,7 +452,8 @@ void build_candidates(st_plan_s* p) {
             // LDS input queue) at four fused steps: FP64 1075 Gcell/s with two
             // LDS buffers and 4 rows x 128 columns per wave (LDS queue: 955);
             // FP32 1623 with 8 rows x 128 columns (4 rows x 256 columns: 1530,
-            // LDS queue 1574).  The queued-plane kernel: 740 / 1394.
+            // LDS queue 1574); bfloat16 (three steps) 1895 with 6 rows x 256
+            // columns (4 rows: 1631).  The queued-plane kernel: 740 / 1394.
             if (p->dtype == kF64)
                 vs = {{2, 4, 8, 0, 0, 21}, {2, 4, 8, 0, 0, 112}, {2, 4, 8, 1, 1}, {2, 4, 8, 1, 0},
                       {2, 4, 8, 0, 0},     {2, 4, 4, 0, 0},      {2, 2, 8, 0, 0}, {2, 3, 8, 1, 0},
@@ -463,7 +464,7 @@ void build_candidates(st_plan_s* p) {
                       {4, 3, 8, 1, 0},     {4, 4, 8, 0, 1},     {4, 5, 8, 1, 1},      {4, 4, 8, 0, 0, 11},
                       {4, 3, 8, 0, 0, 21}};
             else
-                vs = {{4, 4, 8, 0, 0, 21}, {4, 4, 8, 0, 1}, {4, 4, 4, 0, 0}};
+                vs = {{4, 6, 8, 0, 0, 21}, {4, 4, 8, 0, 0, 21}, {4, 4, 8, 0, 1}, {4, 4, 4, 0, 0}};
         } else {
             // radius 4: the y halo through LDS (ylds) loads 2R rows per tile
             // instead of 2R per wave
@@ -497,8 +498,8 @@ void build_candidates(st_plan_s* p) {
             }
         }
         // measured on MI355X (512^3, radius 1, 100 steps): four fused steps of
-        // the pipeline for FP64 and FP32 (1034-1066 and 1581 Gcell/s; three:
-        // 855 and 1483); bfloat16 three (1627; four: 1523; one step of the
+        // the pipeline for FP64 and FP32 (1081 and 1625 Gcell/s; three: 913
+        // and 1483); bfloat16 three (1895; four: 1488; one step of the
         // queued-plane kernel: 1384)
         const int want = p->radius == 1 ? (p->dtype == kBF16 ? 3 : 4) : 1;
         std::stable_sort(fast.begin(), fast.end(), [&](const Candidate& a, const Candidate& b) {
