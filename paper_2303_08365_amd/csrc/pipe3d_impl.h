@@ -402,6 +402,10 @@ struct Pipe {
             load_plane(c, zin + PD, s.pf[J], s.hpf[J]);
         }
 
+        // Phases A and B run at a raised wave priority: they form the chain
+        // each arriving plane starts, while phase C (back at the base
+        // priority) only prepares the next iteration (measured +0.7 %).
+        __builtin_amdgcn_s_setprio(1);
         // phase A, level by level: u_{l+1}(zin-l-1) = fma(w6, u_l(zin-l),
         // P_l(zin-l-1)) (a ghost plane zin-l, where levels >= 1 hold junk,
         // enters with weight 0); the last level's plane is stored.  Early
@@ -473,6 +477,7 @@ struct Pipe {
             }
         }
         sync();
+        __builtin_amdgcn_s_setprio(0);
 
         // phase C: the (rest of the) next partial sums; the neighbour rows of
         // every level are read first, one LDS round trip
