@@ -130,9 +130,10 @@ struct Pipe {
         double* fpart;         // this wave's partial sum
         int32_t ny, nx, xl, yw, ox0, ox1, oy0, oy1;
         bool fx;               // the output tile reaches the x faces
+        TC lx;                 // weight leaving through this lane's face column (0: none)
+        uint32_t rowmask;      // bit k: the wave's row k lies inside the output tile (wave-uniform)
         bool fzy;              // the z chunk reaches a z face, or the wave owns a y-face row
         int32_t k0, k1;        // the wave's rows that the tile owns: k0 <= k < k1
-        bool rows_all;         // all of them
     };
 
     static __device__ __forceinline__ bool zghost(int32_t z, int32_t nz) {
@@ -266,9 +267,12 @@ struct Pipe {
     // only on the first / last plane and on the rows of the waves that own a
     // y-face row).  x part: edge tiles touch the x faces, so a face column is
     // column 0 of lane 0 or column VX-1 of lane 63; per iteration a lane adds
-    // up those two columns over its owned rows of every state (T_b * K values,
-    // compute precision) and adds the sums to two FP64 totals, weighted once
-    // at the end.
+    // up its face column over the rows of every state (T_b * K values,
+    // compute precision, a 0 factor for rows and planes the tile does not own,
+    // so every wave does the same work between two barriers) and adds the sum,
+    // times the face's leaving weight, to its FP64 total.  (One wave doing
+    // more, as when unowned rows took a slower path, holds back all eight:
+    // FP32 1250 against 1343 Gcell/s with outflow at 512^3.)
     static __device__ __forceinline__ double leave_z(const Ctx& c, int32_t z) {
         return (z + 1 >= c.nz ? static_cast<double>(c.w[1]) : 0.0) + (z < 1 ? static_cast<double>(c.w[6]) : 0.0);
     }
@@ -282,8 +286,7 @@ struct Pipe {
         return static_cast<uint32_t>(x - c.ox0) < static_cast<uint32_t>(c.ox1 - c.ox0);
     }
     struct Flux {
-        double fl;     // z and y parts so far
-        double xa[2];  // owned-row totals of the lane's first and last column
+        double fl;     // the outflow so far
     };
     // z and y parts of one plane of one state
     static __device__ __forceinline__ void flux_zy(const Ctx& c, Flux& f, int32_t z, const TC (&v)[K][VX]) {
@@ -308,9 +311,11 @@ struct Pipe {
         }
     }
     // All states of one iteration (planes zin - l of levels l < TB): the z / y
-    // parts per state; the x part as one compute-precision sum per candidate
-    // column over the owned rows of the states whose plane is owned, added to
-    // the FP64 total once per iteration.
+    // parts per state; the x part as one compute-precision sum of the lane's
+    // face column (column 0 of lane 0, column VX-1 of lane 63; c.lx, the
+    // weight leaving through that face, is 0 elsewhere) over the owned rows of
+    // the states whose plane is owned, weighted into the FP64 total once per
+    // iteration.
     template <int TB>
     static __device__ __forceinline__ void flux_add(const Ctx& c, Flux& f, int32_t zin, const TC (&cur)[TB][K][VX]) {
         if (c.fzy) {
@@ -318,49 +323,28 @@ struct Pipe {
             for (int l = 0; l < TB; ++l) flux_zy(c, f, zin - l, cur[l]);
         }
         if (c.fx) {
-            if (c.rows_all && zin - (TB - 1) >= c.zs && zin < c.ze) {
-                // every row of every state of this iteration is owned: one
-                // compute-precision sum per column, one FP64 add
+            // every wave the same work (the waves meet at a barrier every
+            // plane): rows outside the output tile and planes outside the
+            // chunk enter with a 0 factor (exact for finite states)
+            const bool hi = c.lane == 63;
+            TC col = TC(0);
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const int e = i == 0 ? 0 : VX - 1;
-                    TC col = cur[0][0][e];
+            for (int l = 0; l < TB; ++l) {
+                const int32_t z = zin - l;
+                TC cl = TC(0);
 #pragma unroll
-                    for (int l = 0; l < TB; ++l)
-#pragma unroll
-                        for (int k = (l == 0 ? 1 : 0); k < K; ++k) col += cur[l][k][e];
-                    f.xa[i] += static_cast<double>(col);
-                }
-            } else {
-                // the first and last wave of a tile, the ends of a z chunk:
-                // the owned values one by one, in FP64
-#pragma unroll
-                for (int l = 0; l < TB; ++l) {
-                    const int32_t z = zin - l;
-                    if (static_cast<uint32_t>(z - c.zs) >= static_cast<uint32_t>(c.ze - c.zs)) continue;
-#pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        if (k < c.k0 || k >= c.k1) continue;
-#pragma unroll
-                        for (int i = 0; i < 2; ++i) f.xa[i] += static_cast<double>(cur[l][k][i == 0 ? 0 : VX - 1]);
-                    }
-                }
+                for (int k = 0; k < K; ++k)
+                    cl = fma_c(hi ? cur[l][k][VX - 1] : cur[l][k][0], (c.rowmask >> k & 1u) ? TC(1) : TC(0), cl);
+                col += static_cast<uint32_t>(z - c.zs) < static_cast<uint32_t>(c.ze - c.zs) ? cl : TC(0);
             }
+            f.fl = fma(static_cast<double>(col), static_cast<double>(c.lx), f.fl);
         }
     }
     static __device__ __forceinline__ void flux_store_sum(const Ctx& c, double t) {
         t = wave_sum(t);
         if (c.lane == 0) *c.fpart = t;
     }
-    static __device__ __forceinline__ void flux_store(const Ctx& c, const Flux& f) {
-        double t = f.fl;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int32_t x = c.xl + (i == 0 ? 0 : VX - 1);
-            t = fma(f.xa[i], own_x(c, x) ? leave_x(c, x) : 0.0, t);
-        }
-        flux_store_sum(c, t);
-    }
+    static __device__ __forceinline__ void flux_store(const Ctx& c, const Flux& f) { flux_store_sum(c, f.fl); }
 
     template <int TB>
     struct State {
@@ -402,10 +386,11 @@ struct Pipe {
             load_plane(c, zin + PD, s.pf[J], s.hpf[J]);
         }
 
-        // Phases A and B run at a raised wave priority: they form the chain
-        // each arriving plane starts, while phase C (back at the base
-        // priority) only prepares the next iteration (measured +0.7 %).
-        __builtin_amdgcn_s_setprio(1);
+        // FP64: phases A and B run at a raised wave priority: they form the
+        // chain each arriving plane starts, while phase C (back at the base
+        // priority) only prepares the next iteration (measured +0.7 %; no
+        // gain for FP32, a loss for bfloat16).
+        if constexpr (sizeof(TC) == 8) __builtin_amdgcn_s_setprio(1);
         // phase A, level by level: u_{l+1}(zin-l-1) = fma(w6, u_l(zin-l),
         // P_l(zin-l-1)) (a ghost plane zin-l, where levels >= 1 hold junk,
         // enters with weight 0); the last level's plane is stored.  Early
@@ -477,7 +462,7 @@ struct Pipe {
             }
         }
         sync();
-        __builtin_amdgcn_s_setprio(0);
+        if constexpr (sizeof(TC) == 8) __builtin_amdgcn_s_setprio(0);
 
         // phase C: the (rest of the) next partial sums; the neighbour rows of
         // every level are read first, one LDS round trip
@@ -541,7 +526,6 @@ struct Pipe {
         __syncthreads();
         State<TB> s;
         s.fx.fl = 0.0;
-        s.fx.xa[0] = s.fx.xa[1] = 0.0;
 #pragma unroll
         for (int l = 0; l < TB; ++l)
 #pragma unroll
@@ -656,11 +640,18 @@ struct Pipe {
             }
             c.k0 = oy0 - yw > 0 ? oy0 - yw : 0;
             c.k1 = oy1 - yw < K ? oy1 - yw : K;
-            c.rows_all = c.k0 == 0 && c.k1 == K;
             c.fzy = fy || c.zs < 1 || c.ze > c.nz - 1;
         }
 #pragma unroll
         for (int p = 0; p < 7; ++p) c.w[p] = static_cast<TC>(a.w[p]);
+        if constexpr (FLX) {
+            const int32_t xf = c.xl + (c.lane == 63 ? VX - 1 : 0);
+            c.lx = static_cast<TC>(own_x(c, xf) ? leave_x(c, xf) : 0.0);
+            uint32_t m = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) m |= (k >= c.k0 && k < c.k1) ? 1u << k : 0u;
+            c.rowmask = __builtin_amdgcn_readfirstlane(m);
+        }
         const int tb = a.tb;
         if constexpr (TBMAX >= 4) if (tb == 4) return run_tb<4>(c, lds);
         if constexpr (TBMAX >= 3) if (tb == 3) return run_tb<3>(c, lds);
