@@ -14,7 +14,7 @@ import scipy.fft
 
 import oracle
 import synth
-from gpu_helpers import TOL, to_device, to_host
+from gpu_helpers import TOL, check, to_device, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -28,7 +28,7 @@ def _run(u0, offs, w, steps, bc, dtype):
     return g, plan
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_heat3d_512_whole_grid_matches_oracle(dtype):
     # the headline workload as bench.py runs it (default plan, 100 steps),
     # every cell against the oracle on the same (rounded) inputs and weights
@@ -45,6 +45,10 @@ def test_heat3d_512_whole_grid_matches_oracle(dtype):
     err = oracle.rel_l2(got, ref)
     worst = float(np.max(np.abs(got - ref)))
     print(f"heat3d 512^3 {dtype}: rel-L2 {err:.3e}, max |delta| {worst:.3e}", flush=True)
+    if dtype == "bf16":
+        # the non-expansive bound per cell and in rel-L2 (gpu_helpers.check)
+        check(got, ref, dtype, T, "heat3d 512^3 bf16")
+        return
     assert err <= TOL[dtype]
     # per cell: the bar times the largest value (values lie in [0, 2))
     assert worst <= TOL[dtype] * float(np.max(np.abs(ref)))
