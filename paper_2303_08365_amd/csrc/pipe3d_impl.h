@@ -550,6 +550,9 @@ struct Pipe {
                 for (int k = 0; k < K; ++k) strow(none, c.so[k], zero);
             }
             for (int32_t it = 0; it < nit; ++it) step<TB, 0>(c, it, zfirst, s, lds);
+            // the last two iterations' queue loads (planes past the chunk,
+            // never read) land before the work-group's LDS is released
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt: any
         } else {
 #pragma unroll
             for (int p = 0; p < PD; ++p) load_plane(c, zfirst + p, s.pf[p], s.hpf[p]);
