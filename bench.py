@@ -571,7 +571,8 @@ def main():
                    "tile": [info["tile_x"], info["tile_y"], info["tile_z"]],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm",
-                     "kernel": ("pipe3d_kernel" if info.get("pipeline") else
+                     "kernel": ("boxpipe3d_kernel" if info.get("pipeline") and info["kernel"] == 5 else
+                                "pipe3d_kernel" if info.get("pipeline") else
                                 "stream2d_kernel + tess2d_band_kernel" if info.get("tessellated") else
                                 KERNEL_NAMES[info["kernel"]]),
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",

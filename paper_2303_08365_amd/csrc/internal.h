@@ -143,6 +143,17 @@ struct Box3DShape {
 };
 Box3DShape box3d_shape(int dtype, int tb);
 hipError_t launch_box3d(int dtype, bool periodic, bool fast, const Box3DArgs& a, hipStream_t s);
+// two fused steps, partial sums along z, one LDS row exchange per plane
+// (zero rule, whole-vector rows; Box3DArgs.tb = 2)
+struct BoxPipeShape {
+    int vx, k;           // columns and rows per lane
+    int w, h;            // register tile: 64*vx columns x k*waves rows
+    int out_w, out_h;    // owned columns and rows per tile
+    int block;           // threads per work-group
+};
+int boxpipe3d_variants(int dtype);
+BoxPipeShape boxpipe3d_shape(int dtype, int variant);
+hipError_t launch_boxpipe3d(int dtype, int variant, const Box3DArgs& a, hipStream_t s);
 
 // ----------------------------------------------------------------------------
 // variable-coefficient 3D heat step (zero rule) and its adjoint

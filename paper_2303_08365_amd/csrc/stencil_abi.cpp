@@ -155,6 +155,7 @@ struct Candidate {
     Stream3DKey k3{};
     int32_t chunk = 0;  // y chunk (2D) or z chunk (3D); 0 = automatic
     int32_t occ = 0;    // resident work-groups per CU (0 = unknown: assume 2)
+    int32_t bpipe = 0;  // ST_KERNEL_BOX3D, two steps: 0 = box3d_kernel, v + 1 = boxpipe3d variant v
 };
 
 struct BatchGrid {
@@ -326,6 +327,22 @@ bool geob(const st_plan_s* p, const Candidate& c, int tb, GeoB& g) {
     if (tb < 1 || tb > 2) return false;
     if (n[1] * n[2] * elem_bytes(p->dtype) >= (int64_t(1) << 31)) return false;
     if (n[0] >= (int64_t(1) << 30) || n[1] >= (int64_t(1) << 30) || n[2] >= (int64_t(1) << 30)) return false;
+    if (c.bpipe > 0 && tb == 2) {
+        // the partial-sum pipeline: zero rule, whole-vector rows, the grid
+        // at least one register tile wide and high; one work-group of 8
+        // waves per CU (2 waves per SIMD); 5 planes re-streamed per chunk
+        const BoxPipeShape sh = boxpipe3d_shape(p->dtype, c.bpipe - 1);
+        if (p->bc != kZero || n[2] < sh.w || n[1] < sh.h || n[2] % sh.vx != 0) return false;
+        g.tiles_x = static_cast<int32_t>(ceil_div(n[2], sh.out_w));
+        g.tiles_y = static_cast<int32_t>(ceil_div(n[1], sh.out_h));
+        const int64_t per_plane = static_cast<int64_t>(g.tiles_x) * g.tiles_y;
+        int64_t chunk = c.chunk;
+        if (chunk <= 0) chunk = pick_chunk(n[0], per_plane, static_cast<int64_t>(device_cus()), 5, 8);
+        chunk = std::min<int64_t>(chunk, n[0]);
+        g.chunk_z = static_cast<int32_t>(chunk);
+        g.chunks_z = static_cast<int32_t>(ceil_div(n[0], chunk));
+        return per_plane * g.chunks_z < (int64_t(1) << 31);
+    }
     const Box3DShape sh = box3d_shape(p->dtype, tb);
     g.tiles_x = static_cast<int32_t>(ceil_div(n[2], sh.out_w));
     g.tiles_y = static_cast<int32_t>(ceil_div(n[1], sh.h));
@@ -507,9 +524,28 @@ void build_candidates(st_plan_s* p) {
         });
     }
     if (!force_naive && p->ndim == 3 && p->cls == kBox && p->radius == 1) {
-        // one step per pass first: the two-step variant recomputes 2 of every
-        // 4 rows at its first step and measured slower on 512^3 (266 vs 326
-        // Gcell/s FP64, 408 vs 639 FP32); it stays a candidate for the autotuner
+        // FP64 under the zero rule: two steps through the partial-sum
+        // pipeline first (512^3: 425 against 328 Gcell/s for one step per
+        // pass).  Otherwise one step per pass first: the wave-independent
+        // two-step variant recomputes 2 of every 4 rows at its first step
+        // (266 vs 326 Gcell/s FP64, 408 vs 639 FP32), and the pipeline's FP32
+        // and bfloat16 forms are VALU-bound at two steps (633 vs 654, 523 vs
+        // 862): without packed math FP32 runs at the FP64 vector rate, so two
+        // fused steps cost more than a one-step pass's HBM time; they stay
+        // candidates for the autotuner.
+        const auto add_pipe = [&]() {
+            for (int v = 0; v < boxpipe3d_variants(p->dtype); ++v)
+                for (int ch : {0, 16}) {
+                    Candidate c;
+                    c.kernel = ST_KERNEL_BOX3D;
+                    c.tb = 2;
+                    c.chunk = ch;
+                    c.bpipe = v + 1;
+                    GeoB g;
+                    if ((ch == 0 || ch < p->n[0]) && geob(p, c, 2, g)) fast.push_back(c);
+                }
+        };
+        if (p->dtype == kF64) add_pipe();
         for (int tb : {1, 2})
             for (int ch : {0, 16, 32, 64}) {
                 Candidate c;
@@ -519,6 +555,7 @@ void build_candidates(st_plan_s* p) {
                 GeoB g;
                 if ((ch == 0 || ch < p->n[0]) && geob(p, c, tb, g)) fast.push_back(c);
             }
+        if (p->dtype != kF64) add_pipe();
     }
     if (!force_naive && p->ndim == 1 && p->cls == kStar && stream1d_has(p->dtype, p->radius)) {
         // the whole space-time tile in registers: any depth; deeper passes
@@ -680,7 +717,18 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
     }
     if (c.kernel == ST_KERNEL_BOX3D) {
         GeoB g;
-        if (!geob(p, c, tb, g)) return fail(ST_ERR_UNSUPPORTED, "3D box tiling infeasible");
+        // the pipeline takes two-step passes over whole-vector rows; any
+        // other pass of the candidate runs on box3d_kernel (same bits)
+        Candidate cb = c;
+        if (cb.bpipe > 0) {
+            const BoxPipeShape sh = boxpipe3d_shape(p->dtype, cb.bpipe - 1);
+            const bool ok = tb == 2 && p->n[2] % sh.vx == 0 && aligned16(src) && aligned16(dst);
+            if (!ok || !geob(p, cb, tb, g)) {
+                cb.bpipe = 0;
+                cb.chunk = 0;
+            }
+        }
+        if (!geob(p, cb, tb, g)) return fail(ST_ERR_UNSUPPORTED, "3D box tiling infeasible");
         Box3DArgs a;
         std::memset(&a, 0, sizeof(a));
         a.src = src;
@@ -694,6 +742,11 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
         a.chunk_z = g.chunk_z;
         a.tb = tb;
         for (int i = 0; i < p->npoints; ++i) a.w[i] = wcan[i];
+        if (cb.bpipe > 0) {
+            e = launch_boxpipe3d(p->dtype, cb.bpipe - 1, a, s);
+            if (e != hipSuccess) return hip_fail(e, "boxpipe3d launch");
+            return ST_OK;
+        }
         // whole-vector rows; under the zero rule the edge tiles move inward,
         // which needs the grid at least one register tile wide
         const bool fast = vec_ok && (p->bc == kPeriodic || p->n[2] >= box3d_shape(p->dtype, tb).w);
@@ -967,11 +1020,20 @@ void describe(const st_plan_s* p, const Candidate& c, int index, st_plan_info* i
     } else if (c.kernel == ST_KERNEL_BOX3D) {
         GeoB g;
         geob(p, c, c.tb, g);
-        const Box3DShape sh = box3d_shape(p->dtype, c.tb);
-        info->tile_x = sh.out_w;
-        info->tile_y = sh.h;
+        if (c.bpipe > 0) {
+            const BoxPipeShape sh = boxpipe3d_shape(p->dtype, c.bpipe - 1);
+            info->tile_x = sh.out_w;
+            info->tile_y = sh.out_h;
+            info->block = sh.block;
+            info->lds_bytes = 2 * (2 * sh.block / 64 + 2) * sh.w * (p->dtype == kF64 ? 8 : 4);
+            info->pipeline = c.bpipe;
+        } else {
+            const Box3DShape sh = box3d_shape(p->dtype, c.tb);
+            info->tile_x = sh.out_w;
+            info->tile_y = sh.h;
+            info->block = sh.block;
+        }
         info->tile_z = g.chunk_z;
-        info->block = sh.block;
         info->workgroups = static_cast<int64_t>(g.tiles_x) * g.tiles_y * g.chunks_z;
     } else if (c.kernel == ST_KERNEL_STREAM1D) {
         Geo1 g;

@@ -247,9 +247,36 @@ def test_box27_512_sampled_cells(dtype):
     got = to_host(g)
     del g
     tol = 1e-12 if dtype == "f64" else 1e-5
-    for p in [(0, 0, 0), (511, 511, 511), (0, 255, 511), (256, 0, 300), (137, 402, 3), (300, 127, 128)]:
+    # corners, faces, and the pipeline's tile and chunk seams (124-column,
+    # 22-row tiles, 256-plane chunks)
+    for p in [(0, 0, 0), (511, 511, 511), (0, 255, 511), (256, 0, 300), (137, 402, 3), (300, 127, 128),
+              (255, 21, 123), (256, 22, 124), (511, 505, 496)]:
         ref = oracle.sweep_point(u0, offs, w, T, p, bc="zero")
         assert abs(got[p] - ref) <= tol * max(1.0, abs(ref)), p
+
+
+def test_box27_512_fp64_pipeline_whole_grid():
+    # the two-step partial-sum pipeline (the FP64 plan's default for 27-point
+    # boxes) on the whole 512^3 grid, 5 steps (two pipeline passes and one
+    # one-step pass), every cell against the oracle
+    import paper_2303_08365_amd as st
+    import torch
+    n, T = 512, 5
+    offs = synth.box_offsets(3, 1)
+    w = synth.box_mean_weights(3, 1, "f64")
+    u0 = synth.uniform_field((n, n, n), seed=3)
+    plan = st.Plan(offs, (n, n, n), "f64", "zero")
+    info = plan.info()
+    print("plan", info, flush=True)
+    assert info["kernel"] == st.KERNEL_BOX3D and info["pipeline"] > 0 and info["tb"] == 2
+    g = to_device(u0, "f64")
+    plan.run(g, list(w), T, work=torch.empty_like(g))
+    got = to_host(g)
+    del g
+    ref = oracle.sweep(u0, offs, w, T, bc="zero")
+    print(f"rel-L2 {oracle.rel_l2(got, ref):.3e}, max |err| {float(np.max(np.abs(got - ref))):.3e}", flush=True)
+    check(got, ref, "f64", T, "512^3 box pipeline")
+    assert float(np.max(np.abs(got - ref))) <= 1e-13
 
 
 def test_heat2d_512_fp64_100_steps_as_benched():

@@ -256,3 +256,34 @@ def test_3d_box27_all_candidates_match_oracle(dtype, bc, shape):
         results.append(got)
     for k, r in enumerate(results[1:], 1):
         assert np.array_equal(r, results[0]), f"candidate {k} differs bitwise"
+
+
+# 3D boxes, two steps per pass through the partial-sum pipeline (zero rule):
+# several tiles in x and y with ragged last tiles, several z chunks with a
+# short last one, odd step counts (the last pass takes one step on the
+# one-step kernel); every pipeline candidate against the oracle and, bit for
+# bit, against the one-step kernel
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("shape,steps", [((13, 50, 260), 4), ((40, 53, 256), 5), ((9, 70, 384), 3),
+                                         ((35, 49, 512), 2)])
+def test_3d_box27_pipeline_matches_oracle(dtype, shape, steps):
+    import paper_2303_08365_amd as st
+    offs = synth.box_offsets(3, 1)
+    w = _weights(offs, 11, dtype)
+    u0 = synth.uniform_field(shape, seed=12)
+    ref = oracle_ref(u0, offs, w, steps, "zero", dtype)
+    plan = st.Plan(offs, shape, dtype, "zero")
+    cands = plan.candidates()
+    pipes = [k for k, c in enumerate(cands) if c["pipeline"] > 0]
+    assert pipes, f"no pipeline candidate for {shape} {dtype}"
+    k1 = next(k for k, c in enumerate(cands) if c["tb"] == 1 and c["kernel"] == st.KERNEL_BOX3D)
+    one, _ = gpu_sweep(u0, offs, w, steps, "zero", dtype, select={"variant": k1}, plan=plan)
+    # FP64: the pipeline is the plan's default
+    assert (cands[0]["pipeline"] > 0) == (dtype == "f64")
+    for k in pipes:
+        c = cands[k]
+        print(f"box27 pipeline {dtype} {shape} steps {steps} cand {k} variant {c['pipeline']} "
+              f"tile {c['tile_x']}x{c['tile_y']}x{c['tile_z']} wgs {c['workgroups']}", flush=True)
+        got, _ = gpu_sweep(u0, offs, w, steps, "zero", dtype, select={"variant": k}, plan=plan)
+        check(got, ref, dtype, steps, f"cand {k}")
+        assert np.array_equal(got, one), f"candidate {k} differs bitwise from the one-step kernel"
