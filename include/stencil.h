@@ -90,7 +90,7 @@ typedef struct st_plan_s* st_plan;
 #define ST_KERNEL_STREAM3D 2   /* 3D star, planes streamed, LDS row exchange   */
 #define ST_KERNEL_VARCOEF3D 3  /* 3D variable-coefficient heat                 */
 #define ST_KERNEL_STREAM1D 4   /* 1D star, a wave's strip of cells in registers */
-#define ST_KERNEL_BOX3D 5      /* 3D radius-1 box, planes streamed, one step     */
+#define ST_KERNEL_BOX3D 5      /* 3D radius-1 box, planes streamed, 1-2 steps    */
 
 typedef struct {
     int32_t kernel;           /* ST_KERNEL_*                                    */
@@ -106,7 +106,10 @@ typedef struct {
     int32_t pipeline;         /* ST_KERNEL_STREAM3D: 0 = queued planes, else    */
                               /* the partial-sum pipeline (LDS buffers * 10 +   */
                               /* prefetched planes, + 100 when the planes come  */
-                              /* through an LDS queue rather than registers)   */
+                              /* through an LDS queue rather than registers); */
+                              /* ST_KERNEL_BOX3D: 0 = one plane queue per step, */
+                              /* else the two-step partial-sum pipeline (one   */
+                              /* LDS row exchange per plane), variant + 1      */
     int32_t tessellated;      /* ST_KERNEL_STREAM2D: 1 = tessellated tiling     */
                               /* along y (paper Sec. 4.1: triangles, then the   */
                               /* inverted triangles at the chunk junctions, no  */
