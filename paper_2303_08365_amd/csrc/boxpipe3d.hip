@@ -35,7 +35,8 @@
 // and a 32-bit vector offset per row fixed for the pass; rows outside the
 // grid and cells the tile does not own use an offset past the range, so
 // such loads return 0 and such stores are dropped.  Needs the zero rule,
-// nx >= 64*VX, ny >= NW*K, nx % VX == 0 and planes below 2 GiB.
+// nx >= 64*VX, ny >= NW*K, planes below 2 GiB and, for an even VX,
+// nx % VX == 0.
 #include "dev_common.h"
 #include "internal.h"
 
@@ -60,6 +61,10 @@ struct Pipe {
     static constexpr uint32_t kOut = 0x80000000u;       // past the end of any plane (planes < 2 GiB)
     static constexpr int32_t kRsrcWord3 = 0x00020000;  // gfx9: raw 32-bit data
     static constexpr int kNT = 2;                      // stores: non-temporal
+    // An odd lane width cannot keep tile edges on lane boundaries (the edge
+    // tiles touch the grid's edge): then ownership and stores go per element.
+    static constexpr bool kElem = VX % 2 != 0;
+    static constexpr int SO = kElem ? K * VX : K;
 
     struct Ctx {
         const TS* src;
@@ -68,7 +73,7 @@ struct Pipe {
         int64_t plane_elems;
         uint32_t plane_bytes;
         uint32_t lo[R];  // byte offset of the lane's columns in rows yw-1 .. yw+K; kOut outside the grid
-        uint32_t so[K];  // same for the stores of the wave's rows; kOut where the tile owns nothing
+        uint32_t so[SO];  // same for the stores of the wave's rows (per element if kElem); kOut: not owned
         int lane, wave;
         TC w[27];
     };
@@ -94,13 +99,24 @@ struct Pipe {
 
     static __device__ __forceinline__ void ldrow(__amdgpu_buffer_rsrc_t r, uint32_t vo, TC (&v)[VX]) {
         constexpr int kBytes = VX * static_cast<int>(sizeof(TS));
-        static_assert(kBytes == 8 || kBytes % 16 == 0, "rows are read in 8- or 16-byte pieces");
+        static_assert(kBytes == 8 || kBytes % 8 == 0, "rows are read in 8- or 16-byte pieces");
         TS vals[VX];
         if constexpr (kBytes % 16 == 0) {
             u32x4 raw[kBytes / 16];
 #pragma unroll
             for (int i = 0; i < kBytes / 16; ++i)
                 raw[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, vo + 16 * i, 0, 0));
+            __builtin_memcpy(vals, raw, kBytes);
+        } else if constexpr (kBytes > 16) {
+            u32x2 raw[kBytes / 8];
+#pragma unroll
+            for (int i = 0; i < kBytes / 16; ++i) {
+                const u32x4 q = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, vo + 16 * i, 0, 0));
+                raw[2 * i] = u32x2{q[0], q[1]};
+                raw[2 * i + 1] = u32x2{q[2], q[3]};
+            }
+            raw[kBytes / 8 - 1] =
+                __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(r, vo + kBytes - 8, 0, 0));
             __builtin_memcpy(vals, raw, kBytes);
         } else {
             const u32x2 raw = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(r, vo, 0, 0));
@@ -119,6 +135,14 @@ struct Pipe {
             __builtin_memcpy(raw, vals, kBytes);
 #pragma unroll
             for (int i = 0; i < kBytes / 16; ++i) __builtin_amdgcn_raw_buffer_store_b128(raw[i], r, vo + 16 * i, 0, kNT);
+        } else if constexpr (kBytes > 16) {
+            u32x2 raw[kBytes / 8];
+            __builtin_memcpy(raw, vals, kBytes);
+#pragma unroll
+            for (int i = 0; i < kBytes / 16; ++i)
+                __builtin_amdgcn_raw_buffer_store_b128(u32x4{raw[2 * i][0], raw[2 * i][1], raw[2 * i + 1][0], raw[2 * i + 1][1]},
+                                                       r, vo + 16 * i, 0, kNT);
+            __builtin_amdgcn_raw_buffer_store_b64(raw[kBytes / 8 - 1], r, vo + kBytes - 8, 0, kNT);
         } else {
             u32x2 raw;
             __builtin_memcpy(&raw, vals, kBytes);
@@ -133,8 +157,23 @@ struct Pipe {
     }
     static __device__ __forceinline__ void store_plane(const Ctx& c, int32_t z, const TC (&v)[K][VX]) {
         const __amdgpu_buffer_rsrc_t r = plane_out(c, z);
+        if constexpr (kElem) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) strow(r, c.so[k], v[k]);
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int e = 0; e < VX; ++e) {
+                    const TS x = S::narrow(v[k][e]);
+                    if constexpr (sizeof(TS) == 8)
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, c.so[k * VX + e], 0, kNT);
+                    else if constexpr (sizeof(TS) == 4)
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, c.so[k * VX + e], 0, kNT);
+                    else
+                        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, x), r, c.so[k * VX + e], 0, kNT);
+                }
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) strow(r, c.so[k], v[k]);
+        }
     }
 
     // The value left of a row's first column and right of its last.
@@ -239,11 +278,23 @@ struct Pipe {
                           ? static_cast<uint32_t>(y * nx + xl) * kE
                           : kOut;
         }
-        const bool xown = xl >= ox0 && xl + VX <= ox1;
+        if constexpr (kElem) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int32_t y = yw + k;
-            c.so[k] = xown && y >= oy0 && y < oy1 ? static_cast<uint32_t>(y * nx + xl) * kE : kOut;
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int e = 0; e < VX; ++e) {
+                    const int32_t y = yw + k, x = xl + e;
+                    c.so[k * VX + e] = x >= ox0 && x < ox1 && y >= oy0 && y < oy1
+                                           ? static_cast<uint32_t>(y * nx + x) * kE
+                                           : kOut;
+                }
+        } else {
+            const bool xown = xl >= ox0 && xl + VX <= ox1;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int32_t y = yw + k;
+                c.so[k] = xown && y >= oy0 && y < oy1 ? static_cast<uint32_t>(y * nx + xl) * kE : kOut;
+            }
         }
 #pragma unroll
         for (int p = 0; p < 27; ++p) c.w[p] = suni(static_cast<TC>(a.w[p]));
@@ -330,13 +381,13 @@ constexpr BoxPipeShape shape_t() {
 
 }  // namespace bp3d
 
-// Instances per type (columns x rows a lane, 8 waves): FP64 2 x 3 (2 x 4
-// spills), FP32 2 x 6, bfloat16 4 x 4.
-int boxpipe3d_variants(int dtype) { return dtype == kF64 || dtype == kF32 || dtype == kBF16 ? 1 : 0; }
+// Instances per type (columns x rows a lane, 8 waves): FP64 2 x 3 and
+// 3 x 2 (2 x 4 and 3 x 3 spill), FP32 2 x 6, bfloat16 4 x 4.
+int boxpipe3d_variants(int dtype) { return dtype == kF64 ? 2 : (dtype == kF32 || dtype == kBF16 ? 1 : 0); }
 
 BoxPipeShape boxpipe3d_shape(int dtype, int v) {
     switch (dtype) {
-        case kF64: return bp3d::shape_t<double, 2, 3, 8>();
+        case kF64: return v == 0 ? bp3d::shape_t<double, 2, 3, 8>() : bp3d::shape_t<double, 3, 2, 8>();
         case kF32: return bp3d::shape_t<float, 2, 6, 8>();
         default: return bp3d::shape_t<bf16s, 4, 4, 8>();
     }
@@ -345,7 +396,7 @@ BoxPipeShape boxpipe3d_shape(int dtype, int v) {
 hipError_t launch_boxpipe3d(int dtype, int v, const Box3DArgs& a, hipStream_t s) {
     if (static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z <= 0) return hipSuccess;
     switch (dtype) {
-        case kF64: return bp3d::launch_t<double, 2, 3, 8>(a, s);
+        case kF64: return v == 0 ? bp3d::launch_t<double, 2, 3, 8>(a, s) : bp3d::launch_t<double, 3, 2, 8>(a, s);
         case kF32: return bp3d::launch_t<float, 2, 6, 8>(a, s);
         case kBF16: return bp3d::launch_t<bf16s, 4, 4, 8>(a, s);
         default: return hipErrorInvalidValue;

@@ -332,7 +332,7 @@ bool geob(const st_plan_s* p, const Candidate& c, int tb, GeoB& g) {
         // at least one register tile wide and high; one work-group of 8
         // waves per CU (2 waves per SIMD); 5 planes re-streamed per chunk
         const BoxPipeShape sh = boxpipe3d_shape(p->dtype, c.bpipe - 1);
-        if (p->bc != kZero || n[2] < sh.w || n[1] < sh.h || n[2] % sh.vx != 0) return false;
+        if (p->bc != kZero || n[2] < sh.w || n[1] < sh.h || (sh.vx % 2 == 0 && n[2] % sh.vx != 0)) return false;
         g.tiles_x = static_cast<int32_t>(ceil_div(n[2], sh.out_w));
         g.tiles_y = static_cast<int32_t>(ceil_div(n[1], sh.out_h));
         const int64_t per_plane = static_cast<int64_t>(g.tiles_x) * g.tiles_y;
@@ -722,7 +722,7 @@ st_status launch_pass(const st_plan_s* p, const Candidate& c, const void* src, v
         Candidate cb = c;
         if (cb.bpipe > 0) {
             const BoxPipeShape sh = boxpipe3d_shape(p->dtype, cb.bpipe - 1);
-            const bool ok = tb == 2 && p->n[2] % sh.vx == 0 && aligned16(src) && aligned16(dst);
+            const bool ok = tb == 2 && (sh.vx % 2 != 0 || p->n[2] % sh.vx == 0) && aligned16(src) && aligned16(dst);
             if (!ok || !geob(p, cb, tb, g)) {
                 cb.bpipe = 0;
                 cb.chunk = 0;
