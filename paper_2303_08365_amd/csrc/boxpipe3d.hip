@@ -43,7 +43,9 @@
 namespace st {
 namespace bp3d {
 
-template <typename TS, int VX, int K, int NW>
+// PR: level 0 and the LDS write of its plane's edge rows -- what the other
+// waves wait for at the next barrier -- run at wave priority 1.
+template <typename TS, int VX, int K, int NW, bool PR = false>
 struct Pipe {
     using S = Storage<TS>;
     using TC = typename S::TC;
@@ -320,6 +322,7 @@ struct Pipe {
         for (int32_t it = 0; it < nit; ++it) {
             const int32_t zin = zfirst + it;
             __syncthreads();
+            if constexpr (PR) __builtin_amdgcn_s_setprio(1);
             TC u0[R][VX];
 #pragma unroll
             for (int i = 0; i < R; ++i)
@@ -352,6 +355,7 @@ struct Pipe {
                 wb[W + e] = x1[0][e];
                 wb[2 * W + e] = x1[K - 1][e];
             }
+            if constexpr (PR) __builtin_amdgcn_s_setprio(0);
             TC o1[K][VX];
             level(c, u1, u1p, P1, o1);
             store_plane(c, zin - 3, o1);
@@ -359,35 +363,36 @@ struct Pipe {
     }
 };
 
-template <typename TS, int VX, int K, int NW>
+template <typename TS, int VX, int K, int NW, bool PR = false>
 __global__ __launch_bounds__(64 * NW) void boxpipe3d_kernel(const Box3DArgs a) {
-    using P = Pipe<TS, VX, K, NW>;
+    using P = Pipe<TS, VX, K, NW, PR>;
     __shared__ __align__(16) typename P::TC lds[2 * P::BUF];
     P::run(a, lds);
 }
 
-template <typename TS, int VX, int K, int NW>
+template <typename TS, int VX, int K, int NW, bool PR = false>
 hipError_t launch_t(const Box3DArgs& a, hipStream_t s) {
     const int64_t tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z;
-    hipLaunchKernelGGL((boxpipe3d_kernel<TS, VX, K, NW>), dim3(static_cast<unsigned>(tiles)), dim3(64 * NW), 0, s, a);
+    hipLaunchKernelGGL((boxpipe3d_kernel<TS, VX, K, NW, PR>), dim3(static_cast<unsigned>(tiles)), dim3(64 * NW), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename TS, int VX, int K, int NW>
+template <typename TS, int VX, int K, int NW, bool PR = false>
 constexpr BoxPipeShape shape_t() {
-    using P = Pipe<TS, VX, K, NW>;
+    using P = Pipe<TS, VX, K, NW, PR>;
     return BoxPipeShape{VX, K, P::W, P::H, P::OUTW, P::OUTH, 64 * NW};
 }
 
 }  // namespace bp3d
 
-// Instances per type (columns x rows a lane, 8 waves): FP64 2 x 3 and
-// 3 x 2 (2 x 4 and 3 x 3 spill), FP32 2 x 6, bfloat16 4 x 4.
+// Instances per type (columns x rows a lane, 8 waves): FP64 2 x 3 (level 0
+// at wave priority 1: 476 against 472 Gcell/s at 512^3) and 3 x 2 (2 x 4 and
+// 3 x 3 spill), FP32 2 x 6, bfloat16 4 x 4.
 int boxpipe3d_variants(int dtype) { return dtype == kF64 ? 2 : (dtype == kF32 || dtype == kBF16 ? 1 : 0); }
 
 BoxPipeShape boxpipe3d_shape(int dtype, int v) {
     switch (dtype) {
-        case kF64: return v == 0 ? bp3d::shape_t<double, 2, 3, 8>() : bp3d::shape_t<double, 3, 2, 8>();
+        case kF64: return v == 0 ? bp3d::shape_t<double, 2, 3, 8, true>() : bp3d::shape_t<double, 3, 2, 8>();
         case kF32: return bp3d::shape_t<float, 2, 6, 8>();
         default: return bp3d::shape_t<bf16s, 4, 4, 8>();
     }
@@ -396,7 +401,7 @@ BoxPipeShape boxpipe3d_shape(int dtype, int v) {
 hipError_t launch_boxpipe3d(int dtype, int v, const Box3DArgs& a, hipStream_t s) {
     if (static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.chunks_z <= 0) return hipSuccess;
     switch (dtype) {
-        case kF64: return v == 0 ? bp3d::launch_t<double, 2, 3, 8>(a, s) : bp3d::launch_t<double, 3, 2, 8>(a, s);
+        case kF64: return v == 0 ? bp3d::launch_t<double, 2, 3, 8, true>(a, s) : bp3d::launch_t<double, 3, 2, 8>(a, s);
         case kF32: return bp3d::launch_t<float, 2, 6, 8>(a, s);
         case kBF16: return bp3d::launch_t<bf16s, 4, 4, 8>(a, s);
         default: return hipErrorInvalidValue;
