@@ -287,3 +287,32 @@ def test_3d_box27_pipeline_matches_oracle(dtype, shape, steps):
         got, _ = gpu_sweep(u0, offs, w, steps, "zero", dtype, select={"variant": k}, plan=plan)
         check(got, ref, dtype, steps, f"cand {k}")
         assert np.array_equal(got, one), f"candidate {k} differs bitwise from the one-step kernel"
+
+
+# the FP64 box pipeline's edge cases: one and two planes, grids exactly one
+# register tile high (24 rows; 16 for the 3-column form) or wide (128 / 192
+# columns), every step count up to two passes
+@pytest.mark.parametrize("shape", [(1, 24, 192), (2, 24, 128), (3, 25, 130), (2, 16, 192)])
+@pytest.mark.parametrize("steps", [1, 2, 3, 4])
+def test_3d_box27_pipeline_edge_cases(shape, steps):
+    import paper_2303_08365_amd as st
+    offs = synth.box_offsets(3, 1)
+    w = _weights(offs, 13)
+    u0 = synth.uniform_field(shape, seed=14)
+    ref = oracle_ref(u0, offs, w, steps, "zero", "f64")
+    plan = st.Plan(offs, shape, "f64", "zero")
+    cands = plan.candidates()
+    pipes = [k for k, c in enumerate(cands) if c["pipeline"] > 0]
+    if shape[1] >= 24:
+        assert cands[0]["pipeline"] == 1
+    assert pipes
+    k1 = next(k for k, c in enumerate(cands) if c["tb"] == 1 and c["kernel"] == st.KERNEL_BOX3D)
+    one, _ = gpu_sweep(u0, offs, w, steps, "zero", "f64", select={"variant": k1}, plan=plan)
+    check(one, ref, "f64", steps, "one-step kernel")
+    for k in pipes:
+        c = cands[k]
+        print(f"box27 pipeline edge {shape} steps {steps} cand {k} variant {c['pipeline']} "
+              f"tile {c['tile_x']}x{c['tile_y']}x{c['tile_z']}", flush=True)
+        got, _ = gpu_sweep(u0, offs, w, steps, "zero", "f64", select={"variant": k}, plan=plan)
+        check(got, ref, "f64", steps, f"cand {k}")
+        assert np.array_equal(got, one), f"candidate {k} differs bitwise from the one-step kernel"
