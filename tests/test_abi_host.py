@@ -504,6 +504,30 @@ def test_lds_queue_kernels_keep_their_memory_count():
     assert found >= 4, "no LDS-queue kernel in the library"
 
 
+def test_box_pipeline_kernels_do_not_spill():
+    # The 27-point box pipeline carries two levels' planes and partial sums in
+    # registers (225-250 VGPRs at 2 waves per SIMD); the forms that spill
+    # (more rows a lane, the copy-free unrolled loops) measured far slower,
+    # so every instance in the library must use no scratch.
+    import re
+    objdump = "/opt/rocm/llvm/bin/llvm-objdump"
+    if not os.path.exists(objdump):
+        pytest.skip("llvm-objdump is not installed")
+    found = 0
+    with tempfile.TemporaryDirectory() as d:
+        for k, b in enumerate(_gpu_code_objects(st.library_path())):
+            f = os.path.join(d, f"co{k}.o")
+            with open(f, "wb") as fh:
+                fh.write(b)
+            dis = subprocess.run([objdump, "-d", f], capture_output=True, text=True, check=True).stdout
+            for m in re.finditer(r"^[0-9a-f]+ <(_Z\w*boxpipe3d_kernel\w*)>:\n(.*?)(?=^[0-9a-f]+ <|\Z)", dis, re.S | re.M):
+                name, body = m.group(1), m.group(2)
+                found += 1
+                assert "scratch_" not in body, f"{name} spills to scratch"
+                assert "s_barrier" in body, f"{name} has no barrier"
+    assert found >= 4, "no box pipeline kernel in the library"
+
+
 def test_kernels_contain_no_device_function_calls():
     # Every kernel is inlined into one function that ends in s_endpgm: no
     # device-function call, hence no return address.  An earlier build
